@@ -1,0 +1,528 @@
+"""Pins of the FP64 CPU oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: published
+known answers, hand-worked values (tests/golden), closed forms, textbook
+evaluation, brute force and distribution laws.  A plausible mistake (a wrong
+sign, swapped operands, a dropped term, an off-by-one index) fails at least
+one of them.  The paper is arXiv 2106.04034 (GSGP-CUDA); section references
+are to it.
+"""
+import math
+import os
+import random
+
+import numpy as np
+import pytest
+
+from tests import pyphilox
+from tests.conftest import GOLDEN
+
+FLT_MAX = 3.4028234663852886e38
+
+
+# --------------------------------------------------------------------------
+# Philox (counter-based generator that every random draw of the method uses)
+
+def _kat():
+    rows = []
+    for line in open(os.path.join(GOLDEN, "philox_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        v = [int(x, 16) for x in line.split()]
+        rows.append((v[:4], v[4:6], tuple(v[6:10])))
+    return rows
+
+
+def test_philox_known_answers(orc):
+    for ctr, key, out in _kat():
+        assert orc.philox(ctr, key) == out
+        assert pyphilox.philox(ctr, key) == out
+
+
+def test_philox_matches_python_twin(orc):
+    rng = random.Random(7)
+    for _ in range(2000):
+        ctr = [rng.getrandbits(32) for _ in range(4)]
+        key = [rng.getrandbits(32) for _ in range(2)]
+        assert orc.philox(ctr, key) == pyphilox.philox(ctr, key)
+
+
+def test_event_threshold(orc):
+    assert orc.event_threshold(0.0) == 0
+    assert orc.event_threshold(1.0) == 1 << 32
+    assert orc.event_threshold(0.5) == 1 << 31
+    assert orc.event_threshold(0.25) == 1 << 30
+    assert orc.event_threshold(0.8) == 3435973836  # floor(0.8 * 2^32)
+
+
+# --------------------------------------------------------------------------
+# CreatePopulation (Section 2.2, "Initialization")
+
+def test_genome_gene_types_and_values(orc):
+    cfg = orc.Config(pop_size=64, genome_len=127, seed=11, run_id=3)
+    l = 7
+    code, cval = orc.genomes(cfg, l, orc.TAG_POPULATION, 64)
+    key = (cfg.seed, cfg.run_id)
+    tf = pyphilox.threshold(cfg.p_function)
+    tfe = pyphilox.threshold(cfg.p_function + cfg.p_feature)
+    for t in (0, 5, 63):
+        for q in (0, 1, 50, 126):
+            w = pyphilox.philox((q, t, 0, orc.TAG_POPULATION), key)
+            if w[0] < tf:
+                assert code[t, q] == -1 - (w[1] >> 30)
+            elif w[0] < tfe:
+                assert code[t, q] == pyphilox.below(w[1], l)
+            else:
+                assert code[t, q] == orc.GENE_CONST
+                assert cval[t, q] == cfg.erc_lo + (cfg.erc_hi - cfg.erc_lo) * pyphilox.u53(w[2], w[3])
+
+
+def test_genome_frequencies():
+    """Gene-type, function and feature frequencies within 99.9 % binomial
+    intervals over ~1e6 genes (probabilities 0.8 / 0.14 / remainder)."""
+    from oracle import oracle as orc
+    cfg = orc.Config(pop_size=8000, genome_len=127, seed=99)
+    l = 10
+    code, cval = orc.genomes(cfg, l, orc.TAG_POPULATION, 8000)
+    n = code.size
+    z = 3.29
+
+    def within(count, p, total):
+        sd = math.sqrt(total * p * (1 - p))
+        return abs(count - total * p) <= z * sd
+
+    func = code < 0
+    func &= code != orc.GENE_CONST
+    feat = code >= 0
+    const = code == orc.GENE_CONST
+    assert within(func.sum(), 0.80, n)
+    assert within(feat.sum(), 0.14, n)
+    assert within(const.sum(), 0.06, n)
+    nf = int(func.sum())
+    for f in (-1, -2, -3, -4):
+        assert within(int((code == f).sum()), 0.25, nf)
+    nfe = int(feat.sum())
+    for f in range(l):
+        assert within(int((code == f).sum()), 1.0 / l, nfe)
+    v = cval[const]
+    assert v.min() >= -1.0 and v.max() < 1.0
+    assert abs(v.mean()) < z * math.sqrt(1 / 3.0 / v.size)
+    assert np.all(cval[~const] == 0.0)
+
+
+def test_genome_tags_and_runs_differ(orc):
+    cfg = orc.Config(pop_size=16, seed=5, run_id=0)
+    a, _ = orc.genomes(cfg, 4, orc.TAG_POPULATION, 16)
+    b, _ = orc.genomes(cfg, 4, orc.TAG_POOL, 16)
+    cfg.run_id = 1
+    c, _ = orc.genomes(cfg, 4, orc.TAG_POPULATION, 16)
+    assert not np.array_equal(a, b) and not np.array_equal(a, c)
+
+
+# --------------------------------------------------------------------------
+# Interpreter (Section 2.2, "Interpreter")
+
+def _parse_program(tokens):
+    code, cval = [], []
+    for tok in tokens:
+        if tok in "+-*/":
+            code.append({"+": -1, "-": -2, "*": -3, "/": -4}[tok])
+            cval.append(0.0)
+        elif tok.startswith("x"):
+            code.append(int(tok[1:]))
+            cval.append(0.0)
+        else:
+            code.append(-5)
+            cval.append(float(tok[2:]))
+    return code, cval
+
+
+def _golden_programs():
+    out = []
+    for line in open(os.path.join(GOLDEN, "interpreter_programs.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        exp, prog, what = (s.strip() for s in line.split("|", 2))
+        out.append((float(exp), prog.split(), what))
+    return out
+
+
+def test_interpreter_hand_worked(orc):
+    x = np.array([[0.5, -0.25, 2.0]])
+    progs = _golden_programs()
+    assert len(progs) >= 15
+    k = max(len(p) for _, p, _ in progs)
+    for exp, toks, what in progs:
+        code, cval = _parse_program(toks)
+        pad = k - len(code)
+        # padding with skipped functions at the front keeps the value: a
+        # function on an empty stack is skipped (also pins the skip rule)
+        code = [-1] * pad + code
+        cval = [0.0] * pad + cval
+        got = orc.interpret(np.array([code], np.int32), np.array([cval]), x)[0, 0]
+        assert got == exp, (what, got, exp)
+
+
+def _pdiv(a, b):
+    return 1.0 if abs(b) < 1e-6 else a / b
+
+
+def _clamp(r):
+    return FLT_MAX if r > FLT_MAX else (-FLT_MAX if r < -FLT_MAX else r)
+
+
+def _infix(code, cval):
+    """Textbook RPN-to-expression conversion (skips only when < 2 operands);
+    returns a Python expression string of the last valid function."""
+    stack, last = [], "0.0"
+    for g, v in zip(code, cval):
+        if g >= 0:
+            stack.append(f"x[{g}]")
+        elif g == -5:
+            stack.append(repr(float(v)))
+        elif len(stack) >= 2:
+            b = stack.pop()
+            a = stack.pop()
+            expr = {-1: f"C({a} + {b})", -2: f"C({a} - {b})", -3: f"C({a} * {b})",
+                    -4: f"C(D({a}, {b}))"}[g]
+            stack.append(expr)
+            last = expr
+    return last
+
+
+def test_interpreter_random_programs_vs_infix(orc):
+    rng = random.Random(3)
+    l = 5
+    X = np.random.default_rng(1).uniform(-2, 2, size=(40, l))
+    X[0, :] = 0.0  # exercises protected division
+    for _ in range(60):
+        k = rng.randint(1, 40)
+        code, cval = [], []
+        for _ in range(k):
+            u = rng.random()
+            if u < 0.5:
+                code.append(-rng.randint(1, 4))
+                cval.append(0.0)
+            elif u < 0.85:
+                code.append(rng.randrange(l))
+                cval.append(0.0)
+            else:
+                code.append(-5)
+                cval.append(rng.uniform(-3, 3))
+        expr = _infix(code, cval)
+        got = orc.interpret(np.array([code], np.int32), np.array([cval]), X)[0]
+        for c in range(X.shape[0]):
+            want = eval(expr, {"x": list(X[c]), "C": _clamp, "D": _pdiv})
+            assert got[c] == want
+
+
+def test_interpreter_rows_independent(orc):
+    cfg = orc.Config(pop_size=6, seed=4)
+    code, cval = orc.genomes(cfg, 3, orc.TAG_POPULATION, 6)
+    X = np.random.default_rng(2).uniform(-1, 1, size=(9, 3))
+    full = orc.interpret(code, cval, X)
+    for t in range(6):
+        assert np.array_equal(orc.interpret(code[t:t + 1], cval[t:t + 1], X)[0], full[t])
+    for c in range(9):
+        assert np.array_equal(orc.interpret(code, cval, X[c:c + 1])[:, 0], full[:, c])
+
+
+def test_interpreter_finite_on_random_genomes(orc):
+    cfg = orc.Config(pop_size=300, seed=8)
+    code, cval = orc.genomes(cfg, 4, orc.TAG_POPULATION, 300)
+    X = np.random.default_rng(5).uniform(-1, 1, size=(50, 4))
+    S = orc.interpret(code, cval, X)
+    assert np.all(np.isfinite(S)) and np.all(np.abs(S) <= FLT_MAX)
+
+
+# --------------------------------------------------------------------------
+# Logistic squashing of random trees and RMSE fitness (Section 2, 2.2)
+
+def test_sigmoid_closed_forms(orc):
+    x = np.array([0.0, -800.0, 800.0, 1.0, -1.0, 3.5, -20.0, 1e-9])
+    s = orc.sigmoid(x)
+    assert s[0] == 0.5 and s[1] == 0.0 and s[2] == 1.0
+    with np.errstate(over="ignore"):
+        ref = 1.0 / (1.0 + np.exp(-x))
+    assert np.all(np.abs(s - ref) <= 2 * np.spacing(np.abs(ref)))
+    assert abs(s[3] + s[4] - 1.0) <= 2 ** -52
+    assert abs(s[3] - 1 / (1 + math.e ** -1)) <= 2 ** -52
+    assert abs(orc.sigmoid(np.array([math.log(3.0)]))[0] - 0.75) <= 2 ** -53
+
+
+def test_rmse_rows(orc):
+    rng = np.random.default_rng(0)
+    S = rng.normal(size=(5, 33))
+    t = rng.normal(size=33)
+    got = orc.rmse_rows(S, t)
+    want = np.sqrt(np.mean((S - t) ** 2, axis=1))
+    assert np.allclose(got, want, rtol=1e-14, atol=0)
+    tt = np.arange(16) / 1024.0
+    assert orc.rmse_rows(tt[None, :], tt)[0] == 0.0
+    assert orc.rmse_rows((tt + 0.5)[None, :], tt)[0] == 0.5
+    assert orc.rmse_rows(np.zeros((2, 0)), np.zeros(0))[1] == 0.0
+
+
+# --------------------------------------------------------------------------
+# Geometric semantic operators (Section 2; Algorithm 1 GSM)
+
+def _worked_rows():
+    out = []
+    for line in open(os.path.join(GOLDEN, "variation_worked.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        head, o, r = (s.strip() for s in line.split("|"))
+        f = head.split()
+        out.append((f[0], [int(v) for v in f[1:5]], float(f[5]), [float(v) for v in o.split()],
+                    float(r)))
+    return out
+
+
+def test_variation_hand_worked(orc):
+    S_P = np.array([[1.0, 2.0], [0.0, 0.0]])
+    sigR = orc.sigmoid(np.array([[0.0, 0.0], [math.log(3.0), -math.log(3.0)]]))
+    t = np.array([1.0, 2.0])
+    rows = _worked_rows()
+    rec = np.zeros(len(rows), dtype=orc.RECORD_DTYPE)
+    for i, (op, idx, ms, _, _) in enumerate(rows):
+        rec[i] = (orc.OP_XO if op == "XO" else orc.OP_MUT, idx[0], idx[1], idx[2], idx[3], 0, ms)
+    # vary() needs a square parent matrix only through its indices: embed
+    S_big = np.zeros((len(rows), 2))
+    S_big[:2] = S_P
+    O = orc.vary(rec, S_big, sigR)
+    F = orc.rmse_rows(O, t)
+    for i, (_, _, _, o, r) in enumerate(rows):
+        assert np.allclose(O[i], o, rtol=1e-15, atol=1e-15), (i, O[i], o)
+        assert abs(F[i] - r) <= 1e-15 * max(1.0, r), (i, F[i], r)
+
+
+def test_variation_identities_and_bounds(orc):
+    rng = np.random.default_rng(4)
+    m, r, n = 8, 5, 40
+    S = rng.normal(scale=3.0, size=(m, n))
+    R = orc.sigmoid(rng.normal(scale=2.0, size=(r, n)))
+    rec = np.zeros(m, dtype=orc.RECORD_DTYPE)
+    for i in range(m):
+        rec[i] = (orc.OP_MUT, i, -1, i % r, i % r, 0, 0.3)      # R1 == R2
+    assert np.array_equal(orc.vary(rec, S, R), S)
+    for i in range(m):
+        rec[i] = (orc.OP_MUT, i, -1, (i + 1) % r, i % r, 0, 0.0)  # ms == 0
+    assert np.array_equal(orc.vary(rec, S, R), S)
+    for i in range(m):
+        rec[i] = (orc.OP_MUT, i, -1, (i + 1) % r, (i + 2) % r, 0, 0.1)
+    O = orc.vary(rec, S, R)
+    assert np.all(np.abs(O - S) <= 0.1 + 1e-15)
+    for i in range(m):
+        rec[i] = (orc.OP_XO, i, (i + 3) % m, i % r, -1, 0, 0.0)
+    O = orc.vary(rec, S, R)
+    lo = np.minimum(S, S[(np.arange(m) + 3) % m])
+    hi = np.maximum(S, S[(np.arange(m) + 3) % m])
+    assert np.all(O >= lo - 1e-12) and np.all(O <= hi + 1e-12)
+    for i in range(m):
+        rec[i] = (orc.OP_XO, i, i, i % r, -1, 0, 0.0)             # p1 == p2
+    assert np.allclose(orc.vary(rec, S, R), S, rtol=2 ** -52, atol=0)
+    half = orc.sigmoid(np.zeros((1, n)))
+    for i in range(m):
+        rec[i] = (orc.OP_XO, i, (i + 1) % m, 0, -1, 0, 0.0)       # pool tree == 0
+    O = orc.vary(rec, S, half)
+    assert np.allclose(O, 0.5 * (S + S[(np.arange(m) + 1) % m]), rtol=1e-15, atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Variation draws: tournaments and the random-tree / step indices
+
+def test_select_matches_brute_force(orc):
+    cfg = orc.Config(pop_size=50, pool_size=17, tournament_size=4, p_crossover=0.5,
+                     mutation_step=0.1, ms_random=1, seed=1234, run_id=2)
+    F = np.random.default_rng(3).uniform(size=50)
+    F[7] = F[9] = F[11] = F.min() - 1.0  # exact ties: the first drawn wins
+    for gen in (1, 2, 77):
+        rec = orc.select(cfg, gen, F)
+        for i in range(cfg.pop_size):
+            W = pyphilox.words(i, gen, 5 + 2 * 4, cfg.seed, cfg.run_id)
+            cand1 = [pyphilox.below(w, 50) for w in W[5:9]]
+            cand2 = [pyphilox.below(w, 50) for w in W[9:13]]
+
+            def winner(c):
+                best = c[0]
+                for x in c[1:]:
+                    if F[x] < F[best]:
+                        best = x
+                return best
+
+            xo = W[0] < pyphilox.threshold(0.5)
+            d = rec[i]
+            assert d["op"] == (orc.OP_XO if xo else orc.OP_MUT)
+            assert d["p1"] == winner(cand1)
+            assert d["r1"] == pyphilox.below(W[1], 17)
+            if xo:
+                assert d["p2"] == winner(cand2) and d["r2"] == -1 and d["ms"] == 0.0
+            else:
+                assert d["p2"] == -1 and d["r2"] == pyphilox.below(W[2], 17)
+                assert d["ms"] == 0.1 * pyphilox.u53(W[3], W[4])
+
+
+def test_select_rank_frequencies():
+    """Winner rank law of a size-s tournament with replacement:
+    P(rank j) = ((m - j + 1)^s - (m - j)^s) / m^s (rank 1 = best)."""
+    from oracle import oracle as orc
+    from scipy import stats
+    m, s = 32, 4
+    cfg = orc.Config(pop_size=m, pool_size=8, tournament_size=s, p_crossover=0.0, seed=9)
+    F = np.arange(m, dtype=float)[::-1].copy()  # individual m-1 is the best
+    counts = np.zeros(m)
+    for gen in range(1, 400):
+        rec = orc.select(cfg, gen, F)
+        ranks = (m - 1 - rec["p1"])  # rank 0 = best
+        counts += np.bincount(ranks, minlength=m)
+    j = np.arange(1, m + 1)
+    p = ((m - j + 1.0) ** s - (m - j) ** s) / m ** s
+    exp = p * counts.sum()
+    keep = exp >= 5
+    obs = np.append(counts[keep], counts[~keep].sum())
+    ex = np.append(exp[keep], exp[~keep].sum())
+    assert stats.chisquare(obs, ex).pvalue > 1e-3
+
+
+def test_select_size_one_is_uniform_and_paper_mode(orc):
+    from scipy import stats
+    m = 16
+    cfg = orc.Config(pop_size=m, pool_size=4, tournament_size=1, p_crossover=0.0, seed=2)
+    F = np.arange(m, dtype=float)
+    counts = np.zeros(m)
+    for gen in range(1, 300):
+        counts += np.bincount(orc.select(cfg, gen, F)["p1"], minlength=m)
+    assert stats.chisquare(counts).pvalue > 1e-3
+    cfg = orc.Config(pop_size=m, pool_size=4, tournament_size=0, p_crossover=0.0, seed=2)
+    rec = orc.select(cfg, 1, F)
+    assert np.array_equal(rec["p1"], np.arange(m)) and np.all(rec["op"] == orc.OP_MUT)
+
+
+# --------------------------------------------------------------------------
+# Survival with elitism (Section 2.2 "Survival")
+
+def test_survival_rules(orc):
+    m, n = 5, 3
+    SP = np.arange(m * n, dtype=float).reshape(m, n)
+    SO = -np.arange(m * n, dtype=float).reshape(m, n)
+    SPt = SP[:, :2].copy()
+    SOt = SO[:, :2].copy()
+    F_P = np.array([3.0, 1.0, 2.0, 1.0, 5.0])
+    Ft_P = F_P * 10
+    F_O = np.array([4.0, 2.0, 7.0, 7.0, 1.5])
+    Ft_O = F_O * 10
+    copied, src, dst = orc.survive(F_P, Ft_P, F_O, Ft_O, SP, SO, SPt, SOt)
+    assert (copied, src, dst) == (1, 1, 2)  # first argmin parent, first argmax offspring
+    assert np.array_equal(SO[2], SP[1]) and np.array_equal(SOt[2], SPt[1])
+    assert F_O[2] == 1.0 and Ft_O[2] == 10.0
+    F_O2 = np.array([4.0, 1.0, 7.0, 7.0, 1.5])  # tie: parent not strictly better
+    copied, _, _ = orc.survive(F_P, Ft_P, F_O2, F_O2 * 10, SP, SO, SPt, SOt)
+    assert copied == 0
+
+
+# --------------------------------------------------------------------------
+# Whole runs (Algorithm 1)
+
+def _small_data(n_tr=30, n_te=10, l=3, seed=0):
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(-1, 1, size=(n_tr + n_te, l))
+    y = X[:, 0] * X[:, 1] + np.sin(X[:, 2])
+    return X[:n_tr], y[:n_tr], X[n_tr:], y[n_tr:]
+
+
+def test_run_elitism_monotone_and_consistent(orc):
+    cfg = orc.Config(pop_size=24, pool_size=16, seed=21)
+    Xtr, ytr, Xte, yte = _small_data()
+    res = orc.run(cfg, Xtr, ytr, Xte, yte, 25, keep_semantics=True)
+    best = [s["best_train_rmse"] for s in res.stats]
+    assert all(b2 <= b1 for b1, b2 in zip(best, best[1:]))
+    for g in range(26):
+        Str, Ste = res.S_hist[g]
+        assert np.allclose(res.F_hist[g], np.sqrt(np.mean((Str - ytr) ** 2, axis=1)), rtol=1e-13)
+        assert np.allclose(res.Ft_hist[g], np.sqrt(np.mean((Ste - yte) ** 2, axis=1)), rtol=1e-13)
+    for g in range(1, 26):
+        copied, src, dst = res.elite[g - 1]
+        if copied:
+            assert np.array_equal(res.S_hist[g][0][dst], res.S_hist[g - 1][0][src])
+    assert res.elite[:, 0].sum() > 0
+
+
+def test_run_deterministic_and_thread_independent(orc):
+    cfg = orc.Config(pop_size=20, pool_size=12, seed=5)
+    Xtr, ytr, Xte, yte = _small_data(seed=1)
+    orc.set_threads(1)
+    a = orc.run(cfg, Xtr, ytr, Xte, yte, 8)
+    orc.set_threads(4)
+    b = orc.run(cfg, Xtr, ytr, Xte, yte, 8)
+    assert np.array_equal(a.S_train, b.S_train) and np.array_equal(a.records, b.records)
+    assert np.array_equal(a.F, b.F)
+
+
+def test_run_drive_reproduces(orc):
+    cfg = orc.Config(pop_size=16, pool_size=8, seed=6)
+    Xtr, ytr, Xte, yte = _small_data(seed=2)
+    a = orc.run(cfg, Xtr, ytr, Xte, yte, 6)
+    b = orc.run(cfg, Xtr, ytr, Xte, yte, 6, drive=(a.records, a.elite))
+    assert np.array_equal(a.S_train, b.S_train) and np.array_equal(a.F, b.F)
+
+
+# --------------------------------------------------------------------------
+# Lineage reconstruction (Section 2.1 stage 3; Algorithm 1 "Return")
+
+def _brute(res, cfg, g, i, X, orc):
+    """Recursive evaluation without memoisation, straight from the definitions."""
+    m = cfg.pop_size
+    if g == 0:
+        return orc.interpret(res.code[i:i + 1], res.cval[i:i + 1], X)[0]
+    copied, src, dst = res.elite[g - 1]
+    if copied and i == dst:
+        return _brute(res, cfg, g - 1, int(src), X, orc)
+    d = res.records[g - 1][i]
+
+    def R(j):
+        return orc.sigmoid(orc.interpret(res.code[m + j:m + j + 1], res.cval[m + j:m + j + 1], X))[0]
+
+    if d["op"] == orc.OP_XO:
+        r = R(int(d["r1"]))
+        return _brute(res, cfg, g - 1, int(d["p1"]), X, orc) * r + \
+            _brute(res, cfg, g - 1, int(d["p2"]), X, orc) * (1.0 - r)
+    return _brute(res, cfg, g - 1, int(d["p1"]), X, orc) + float(d["ms"]) * (
+        R(int(d["r1"])) - R(int(d["r2"])))
+
+
+def test_reconstruct_brute_force(orc):
+    cfg = orc.Config(pop_size=4, pool_size=4, seed=17)
+    Xtr, ytr, Xte, yte = _small_data(n_tr=5, n_te=3, seed=3)
+    G = 5
+    res = orc.run(cfg, Xtr, ytr, Xte, yte, G, keep_semantics=True)
+    for i in range(4):
+        bf = _brute(res, cfg, G, i, Xtr, orc)
+        assert np.array_equal(bf, res.S_train[i])
+        assert np.array_equal(orc.reconstruct(res, cfg, G, i, Xtr), res.S_train[i])
+        assert np.array_equal(orc.reconstruct(res, cfg, G, i, Xte), res.S_test[i])
+    Xnew = np.random.default_rng(9).uniform(-1, 1, size=(7, 3))
+    for g in (0, 2, G):
+        for i in range(4):
+            assert np.array_equal(orc.reconstruct(res, cfg, g, i, Xnew), _brute(res, cfg, g, i, Xnew, orc))
+
+
+def test_reconstruct_mutation_only_closed_form(orc):
+    """Paper loop (mutate every individual, no selection): individual i after
+    G generations is T0[i] + sum_g ms_g (sigma(R_u_g) - sigma(R_v_g)) unless an
+    elite copy interrupts its line."""
+    cfg = orc.Config(pop_size=6, pool_size=5, tournament_size=0, p_crossover=0.0,
+                     ms_random=1, seed=23)
+    Xtr, ytr, Xte, yte = _small_data(n_tr=12, n_te=4, seed=4)
+    G = 10
+    res = orc.run(cfg, Xtr, ytr, Xte, yte, G)
+    m = cfg.pop_size
+    sig = orc.sigmoid(orc.interpret(res.code[m:], res.cval[m:], Xtr))
+    for i in range(m):
+        if any(res.elite[g, 0] and res.elite[g, 2] == i for g in range(G)):
+            continue
+        val = orc.interpret(res.code[i:i + 1], res.cval[i:i + 1], Xtr)[0].copy()
+        for g in range(G):
+            d = res.records[g][i]
+            assert d["p1"] == i and d["op"] == orc.OP_MUT
+            val += float(d["ms"]) * (sig[int(d["r1"])] - sig[int(d["r2"])])
+        assert np.allclose(val, res.S_train[i], rtol=1e-12, atol=1e-12)
