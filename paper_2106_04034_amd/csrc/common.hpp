@@ -1,0 +1,128 @@
+// Internal structures shared by the HIP kernels and the host runtime of
+// libgsgp.so.  Nothing here is part of the public ABI (include/gsgp.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gsgp.h"
+
+namespace gsgp {
+
+// Canonical case chunk: fitness partial sums are formed over these runs of
+// consecutive cases of one segment (train or test), in a fixed order, and
+// combined in FP64 in chunk order.  Launch shapes never change the chunking,
+// so fitness bits (and therefore selection) do not depend on tuning.
+constexpr int kChunk = 512;
+// Each segment (train, test) of a semantic row is padded with zeros to a
+// multiple of this many cases; rows therefore start 256-byte aligned.
+constexpr int kSegPad = 64;
+constexpr int kWave = 64;
+constexpr int kMaxTournament = 64;
+// Deepest stack (values, top included) a compiled genome may need: the
+// interpreter keeps depth - 1 values per lane in at most 64 KiB of LDS.
+constexpr int kMaxStack = 65;
+
+// Compiled genome op word: bits 0..2 kind, bits 3..15 stack depth before
+// the op, bits 16..31 feature index.
+enum OpKind : int32_t { kPushFeature = 0, kPushConst = 1, kAdd = 2, kSub = 3, kMul = 4, kDiv = 5 };
+
+// Per-run device state words.
+enum StateWord : int {
+  kStGen = 0,           // last completed generation
+  kStDone = 1,          // arrival counter of the survival kernel's blocks
+  kStReplaySelect = 2,  // 1: variation draws are supplied, do not draw
+  kStReplayElite = 3,   // 1: survival decisions are supplied
+  kStMaxDepth = 4,      // deepest stack of the compiled genomes
+  kStNonFinite = 5,     // set when X or y holds NaN / Inf
+  kStWords = 8
+};
+
+// Everything a kernel needs to know about one run; lives in the workspace.
+struct RunDev {
+  void* S[2];               // population semantics ping-pong, [m][ld], storage type
+  void* sigR;               // squashed pool semantics, [r][ld]
+  void* y;                  // target, [ld], storage type, zero pads
+  double* X;                // features, feature-major [l][ld], zero pads
+  double* part;             // chunk partial sums of squared residuals, [nch][m]
+  double* F[2];             // train RMSE ping-pong, [m]
+  double* Ft[2];            // test RMSE ping-pong, [m]
+  gsgp_record* rec;         // variation draws, [gmax][m]; generation g at g - 1
+  gsgp_gen_stats* stats;    // [gmax + 1]
+  gsgp_gen_stats* elite_in; // supplied survival decisions, [gmax]
+  int32_t* code;            // genomes, [m + r][k]
+  double* cval;             // [m + r][k]
+  int32_t* ops;             // compiled genomes, [m + r][k]
+  double* opv;              // [m + r][k]
+  int32_t* nops;            // [m + r]
+  int32_t* state;           // [kStWords]
+  int64_t n_train, n_test;  // real cases
+  int64_t tr_pad, te_pad;   // padded segment lengths
+  int64_t ld;               // row stride (tr_pad + te_pad)
+  int32_t l;                // features
+  int32_t nch_tr, nch_te, nch;  // chunks per segment and in total
+  uint32_t run_id;
+  int32_t surv_blk0, surv_blks; // survival kernel blocks of this run
+  int32_t pad0;
+  int64_t vary_task0;       // first task of this run in the variation launch
+  int64_t interp_task0;     // first task of this run in the interpreter launch
+  int64_t col0;             // first padded column of this run (data prep)
+};
+
+// Run-independent parameters, passed by value to every kernel.
+struct Params {
+  int32_t m, r, k, gmax;
+  int32_t tsize, ms_random;
+  int32_t n_runs, precision;
+  uint64_t t_xo, t_func, t_feat;  // event thresholds floor(p * 2^32)
+  double ms, erc_lo, erc_hi;
+  uint32_t seed;
+  int32_t pad;
+};
+
+// Launch shape of the variation kernel.
+struct VaryLaunch {
+  int32_t waves;         // waves per block
+  int32_t opb;           // offspring per block task
+  int32_t ogroups;       // ceil(m / opb)
+  int32_t remap;         // 1: XCD-aware block order
+  int64_t total_tasks;   // sum over runs of nch * ogroups
+  int64_t grid;          // blocks launched
+};
+
+enum SurviveMode : int32_t { kSurvInit = 0, kSurvGen = 1, kSurvSelectOnly = 2 };
+
+// Host-side launchers (kernels.hip).  All enqueue on `s` and return the
+// launch status.
+hipError_t launch_prep(const RunDev* d_runs, const Params& p, int64_t total_cols,
+                       const double* const* Xsrc, const double* const* ysrc, hipStream_t s);
+hipError_t launch_set_state(const RunDev* d_runs, int32_t n_runs, int32_t word, int32_t value,
+                            hipStream_t s);
+hipError_t launch_genome(const RunDev* d_runs, const Params& p, hipStream_t s);
+hipError_t launch_compile(const RunDev* d_runs, const Params& p, hipStream_t s);
+hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t total_tasks, int depth,
+                            hipStream_t s);
+hipError_t launch_vary(const RunDev* d_runs, const Params& p, const VaryLaunch& lc, bool rows_only,
+                       hipStream_t s);
+hipError_t launch_fitness(const RunDev* d_runs, const Params& p, bool init, hipStream_t s);
+hipError_t launch_survive(const RunDev* d_runs, const Params& p, int32_t total_blocks, int mode,
+                          hipStream_t s);
+// Reconstruction helpers.
+hipError_t launch_transpose(const double* X, int64_t n, int32_t l, double* Xfm, int64_t ld,
+                            hipStream_t s);
+hipError_t launch_interpret_list(const int32_t* ops, const double* opv, const int32_t* nops,
+                                 int32_t k, const int32_t* prog, const int32_t* squash,
+                                 int32_t nprog, const double* Xfm, int64_t ld, int64_t n,
+                                 double* out, int depth, hipStream_t s);
+struct ReplayNode {
+  int32_t op;     // 0 mutation, 1 crossover, 2 copy
+  int32_t a, b;   // source slots (previous generation); b = -1 unless crossover
+  int32_t r1, r2; // pool slots
+  int32_t out;    // destination slot
+  double ms;
+};
+hipError_t launch_replay_nodes(const ReplayNode* nodes, int32_t nnodes, const double* prev,
+                               const double* pool, double* next, int64_t ld, int64_t n,
+                               hipStream_t s);
+
+}  // namespace gsgp

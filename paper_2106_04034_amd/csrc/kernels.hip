@@ -1,0 +1,978 @@
+// HIP kernels of the GSGP hot path for gfx950 (MI355X, CDNA4, wave64).
+//
+// Method: "GSGP-CUDA - a CUDA framework for Geometric Semantic Genetic
+// Programming" (Trujillo et al., arXiv 2106.04034), Algorithm 1 and the
+// Section 2.2 paragraphs on initialization, the interpreter, fitness, GSM and
+// survival.  The paper's own CUDA design (one thread per individual for the
+// interpreter and the fitness, cuBLAS I?AMIN / I?AMAX for survival) is prior
+// art; the mapping here is:
+//   k_genome     one thread per gene, counter-based Philox draws;
+//   k_compile    one thread per genome: drops the functions the interpreter
+//                would skip and the pushes after the last function, and
+//                records every op's stack depth;
+//   k_interpret  one wavefront per (program, 128 cases): the compiled
+//                program is wave-uniform (no divergence), lanes own cases,
+//                the top of stack lives in registers and the rest of the
+//                stack in a lane-strided LDS column;
+//   k_vary       the hot loop: every offspring row of one 512-case chunk is
+//                formed from its parent and pool rows with 16-byte loads and
+//                non-temporal 16-byte stores, and the chunk's squared
+//                residual sum is reduced across the wave with xor shuffles;
+//                blocks on one XCD share a chunk so distinct parent and pool
+//                rows are fetched from HBM about once per chunk;
+//   k_fitness    one wavefront per offspring combines chunk sums in FP64;
+//   k_survive    argmin / argmax with lowest-index ties, elite row copy,
+//                per-generation summary and the next generation's tournaments.
+// All kernels are compiled without floating-point contraction so that the
+// per-element arithmetic matches the method's definitions operation by
+// operation.
+#include <float.h>
+#include <math.h>
+
+#include "common.hpp"
+
+namespace gsgp {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct VecOf;
+template <>
+struct VecOf<float> {
+  typedef f4 type;
+  static constexpr int N = 4;
+};
+template <>
+struct VecOf<double> {
+  typedef d2 type;
+  static constexpr int N = 2;
+};
+
+constexpr double kFltMax = 3.4028234663852886e38;  // largest finite binary32 value
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011): ten rounds of two
+// 32x32 -> 64-bit products with a Weyl key schedule.
+struct Words4 {
+  uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint32_t lo0 = 0xD2511F53u * c0;
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t x0 = hi1 ^ c1 ^ k0;
+    const uint32_t x2 = hi0 ^ c3 ^ k1;
+    c0 = x0;
+    c1 = lo1;
+    c2 = x2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return Words4{c0, c1, c2, c3};
+}
+
+// Integer in [0, n) by multiply-shift of one 32-bit word.
+__device__ __forceinline__ int32_t draw_below(uint32_t w, uint32_t n) {
+  return (int32_t)(((uint64_t)w * (uint64_t)n) >> 32);
+}
+
+// Uniform in [0, 1) on the 2^-53 grid from two words (27 + 26 bits).
+__device__ __forceinline__ double draw_u53(uint32_t a, uint32_t b) {
+  const double hi = (double)(a >> 5);
+  const double lo = (double)(b >> 6);
+  return (hi * 67108864.0 + lo) * (1.0 / 9007199254740992.0);
+}
+
+// ---------------------------------------------------------------------------
+// Run lookup: runs are laid out in launch order; find the last run whose
+// first task is <= t.  Single-run launches skip the search.
+template <typename F>
+__device__ __forceinline__ int find_run(int n_runs, int64_t t, F first_of) {
+  if (n_runs == 1) return 0;
+  int lo = 0, hi = n_runs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first_of(mid) <= t)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// Data preparation: FP64 row-major cases -> feature-major padded X, target in
+// the storage type, zero pads, non-finite detection.  One thread per padded
+// column of every run.
+template <typename T>
+__global__ __launch_bounds__(256) void k_prep(const RunDev* __restrict__ runs, Params p,
+                                              int64_t total, const double* const* __restrict__ src) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const int run = find_run(p.n_runs, g, [&](int r) { return runs[r].col0; });
+  const RunDev& R = runs[run];
+  const int64_t col = g - R.col0;
+  const double* Xs = nullptr;
+  const double* ys = nullptr;
+  int64_t row = -1;
+  if (col < R.n_train) {
+    Xs = src[4 * run + 0];
+    ys = src[4 * run + 1];
+    row = col;
+  } else if (col >= R.tr_pad && col < R.tr_pad + R.n_test) {
+    Xs = src[4 * run + 2];
+    ys = src[4 * run + 3];
+    row = col - R.tr_pad;
+  }
+  bool bad = false;
+  for (int f = 0; f < R.l; ++f) {
+    const double v = (row >= 0) ? Xs[row * R.l + f] : 0.0;
+    bad |= !isfinite(v);
+    R.X[(int64_t)f * R.ld + col] = v;
+  }
+  const double yv = (row >= 0) ? ys[row] : 0.0;
+  bad |= !isfinite(yv) || fabs(yv) > kFltMax;
+  ((T*)R.y)[col] = (T)yv;
+  if (bad) atomicOr(&R.state[kStNonFinite], 1);
+}
+
+// ---------------------------------------------------------------------------
+// CreatePopulation (Algorithm 1; Section 2.2 "Initialization"): gene q of
+// tree t draws Philox counter (q, t, 0, tag), key (seed, run), tag 1 for the
+// population and 2 for the random-tree pool.  Word 0 picks the gene type
+// against the cumulative thresholds, word 1 the function or feature, words 2
+// and 3 the constant.
+__global__ __launch_bounds__(256) void k_genome(const RunDev* __restrict__ runs, Params p,
+                                                int64_t total) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const int64_t per_run = (int64_t)(p.m + p.r) * p.k;
+  const int run = (int)(g / per_run);
+  const int64_t local = g - (int64_t)run * per_run;
+  const int row = (int)(local / p.k);
+  const int q = (int)(local - (int64_t)row * p.k);
+  const RunDev& R = runs[run];
+  const uint32_t tag = row < p.m ? 1u : 2u;
+  const uint32_t t = row < p.m ? (uint32_t)row : (uint32_t)(row - p.m);
+  const Words4 w = philox4x32_10((uint32_t)q, t, 0u, tag, p.seed, R.run_id);
+  int32_t code;
+  double val = 0.0;
+  if ((uint64_t)w.w0 < p.t_func) {
+    code = -1 - (int32_t)(w.w1 >> 30);
+  } else if ((uint64_t)w.w0 < p.t_feat) {
+    code = draw_below(w.w1, (uint32_t)R.l);
+  } else {
+    const double u = draw_u53(w.w2, w.w3);
+    const double span = p.erc_hi - p.erc_lo;
+    const double scaled = span * u;
+    code = -5;
+    val = p.erc_lo + scaled;
+  }
+  R.code[local] = code;
+  R.cval[local] = val;
+}
+
+// Compile a genome: drop the functions the stack machine would skip (fewer
+// than two operands) and everything after the last function that runs, and
+// store each op's stack depth so the interpreter needs no depth counter.
+// One thread per genome; also records the deepest stack per run.
+__global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs, Params p,
+                                                 int32_t total) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const int rows = p.m + p.r;
+  const int run = g / rows;
+  const int prog = g - run * rows;
+  const RunDev& R = runs[run];
+  const int32_t* code = R.code + (int64_t)prog * p.k;
+  const double* cval = R.cval + (int64_t)prog * p.k;
+  int32_t* ops = R.ops + (int64_t)prog * p.k;
+  double* opv = R.opv + (int64_t)prog * p.k;
+  int depth = 0, n = 0, last = 0, deepest = 0;
+  for (int q = 0; q < p.k; ++q) {
+    const int32_t c = code[q];
+    if (c >= 0) {
+      ops[n] = kPushFeature | (depth << 3) | (c << 16);
+      opv[n] = 0.0;
+      ++n;
+      ++depth;
+    } else if (c == -5) {
+      ops[n] = kPushConst | (depth << 3);
+      opv[n] = cval[q];
+      ++n;
+      ++depth;
+    } else {
+      if (depth < 2) continue;
+      ops[n] = (kAdd + (-1 - c)) | (depth << 3);
+      opv[n] = 0.0;
+      ++n;
+      --depth;
+      last = n;
+    }
+    deepest = depth > deepest ? depth : deepest;
+  }
+  R.nops[prog] = last;
+  atomicMax(&R.state[kStMaxDepth], deepest);
+}
+
+// Evaluate one compiled program on V cases per lane (Section 2.2
+// "Interpreter").  The op stream is wave-uniform.  tos holds the top of the
+// stack; slot d of the rest lives at stk[(d * V + v) * 64 + lane].  The value
+// of the program is the output of its last function (the Out register), 0.0
+// if none runs.
+template <int V>
+__device__ __forceinline__ void eval_program(const int32_t* __restrict__ ops,
+                                             const double* __restrict__ opv, int n,
+                                             const double* __restrict__ X, int64_t ld,
+                                             const int64_t (&col)[V], const bool (&ok)[V],
+                                             double* __restrict__ stk, int lane, double (&out)[V]) {
+  double tos[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) tos[v] = 0.0;
+  for (int j = 0; j < n; ++j) {
+    const int w = uni(ops[j]);
+    const int kind = w & 7;
+    const int d = (w >> 3) & 0x1FFF;
+    if (kind <= kPushConst) {
+      if (d > 0) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) stk[((d - 1) * V + v) * kWave + lane] = tos[v];
+      }
+      if (kind == kPushFeature) {
+        const int64_t base = (int64_t)((uint32_t)w >> 16) * ld;
+#pragma unroll
+        for (int v = 0; v < V; ++v) tos[v] = ok[v] ? X[base + col[v]] : 0.0;
+      } else {
+        const double c = opv[j];
+#pragma unroll
+        for (int v = 0; v < V; ++v) tos[v] = c;
+      }
+    } else {
+      double a[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) a[v] = stk[((d - 2) * V + v) * kWave + lane];
+      if (kind == kAdd) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) tos[v] = a[v] + tos[v];
+      } else if (kind == kSub) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) tos[v] = a[v] - tos[v];
+      } else if (kind == kMul) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) tos[v] = a[v] * tos[v];
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) tos[v] = (fabs(tos[v]) < 1e-6) ? 1.0 : a[v] / tos[v];
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const double r = tos[v];
+        tos[v] = r > kFltMax ? kFltMax : (r < -kFltMax ? -kFltMax : r);
+      }
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < V; ++v) out[v] = tos[v];
+}
+
+constexpr int kInterpV = 2;  // cases per lane
+
+// ComputeSemantics(P) and ComputeSemantics(R) (Algorithm 1): one wavefront
+// per (program, block of 128 cases).  Pool rows are squashed by the logistic
+// function (the random functions R_u of GSM, Section 2) before storage.
+// Padding columns are written as exact zeros.
+template <typename T>
+__global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ runs, Params p,
+                                                   int64_t total, int depth) {
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x & 63;
+  const int wave = uni(threadIdx.x >> 6);
+  const int64_t task = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+  if (task >= total) return;
+  const int run = find_run(p.n_runs, task, [&](int r) { return runs[r].interp_task0; });
+  const RunDev& R = runs[run];
+  const int64_t local = task - R.interp_task0;
+  const int rows = p.m + p.r;
+  const int64_t cb = local / rows;
+  const int prog = (int)(local - cb * rows);
+  const int64_t ld = R.ld;
+  int64_t col[kInterpV];
+  bool ok[kInterpV];
+#pragma unroll
+  for (int v = 0; v < kInterpV; ++v) {
+    col[v] = cb * (kWave * kInterpV) + v * kWave + lane;
+    ok[v] = col[v] < ld;
+  }
+  double out[kInterpV];
+  double* stk = lds + (int64_t)wave * depth * kInterpV * kWave;
+  eval_program<kInterpV>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k,
+                         uni(R.nops[prog]), R.X, ld, col, ok, stk, lane, out);
+  T* dst = prog < p.m ? (T*)R.S[0] + (int64_t)prog * ld : (T*)R.sigR + (int64_t)(prog - p.m) * ld;
+#pragma unroll
+  for (int v = 0; v < kInterpV; ++v) {
+    if (!ok[v]) continue;
+    const int64_t c = col[v];
+    const bool real = c < R.n_train || (c >= R.tr_pad && c < R.tr_pad + R.n_test);
+    double val = out[v];
+    if (prog >= p.m) val = 1.0 / (1.0 + exp(-val));
+    dst[c] = real ? (T)val : (T)0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Wave reductions.  xor butterflies give every lane the same bits because
+// each step adds the same two operands in both partner lanes.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Compensated combination of Kahan pairs (value = s - c) with Knuth's
+// two-sum: exact error of s1 + s2 is folded into the compensation term.
+__device__ __forceinline__ void wave_sum_kahan(float& s, float& c) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const float s2 = __shfl_xor(s, o, kWave);
+    const float c2 = __shfl_xor(c, o, kWave);
+    const float sum = s + s2;
+    const float bp = sum - s;
+    const float err = (s - (sum - bp)) + (s2 - bp);
+    c = (c + c2) - err;
+    s = sum;
+  }
+}
+
+// Sum over one chunk of (o - t)^2 in the canonical order: each lane adds its
+// elements in address order, then the wave butterfly.  FP32 forms fall back
+// to FP64 when a square overflows.
+template <typename T, int PREC, int NJ, typename VT>
+__device__ __forceinline__ double chunk_sse(const VT (&o)[NJ], const VT (&t)[NJ], const bool (&ok)[NJ]) {
+  constexpr int N = VecOf<T>::N;
+  if constexpr (PREC == GSGP_FP64) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      if (!ok[j]) continue;
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        const double e = o[j][c] - t[j][c];
+        s += e * e;
+      }
+    }
+    return wave_sum(s);
+  } else {
+    double total;
+    if constexpr (PREC == GSGP_FP32) {
+      float s = 0.0f;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        if (!ok[j]) continue;
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+          const float e = o[j][c] - t[j][c];
+          s += e * e;
+        }
+      }
+      s = wave_sum(s);
+      total = (double)s;
+    } else {
+      float s = 0.0f, comp = 0.0f;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        if (!ok[j]) continue;
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+          const float e = o[j][c] - t[j][c];
+          const float y = e * e - comp;
+          const float u = s + y;
+          comp = (u - s) - y;
+          s = u;
+        }
+      }
+      wave_sum_kahan(s, comp);
+      total = (double)s - (double)comp;
+    }
+    if (!isfinite(total)) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        if (!ok[j]) continue;
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+          const double e = (double)o[j][c] - (double)t[j][c];
+          s += e * e;
+        }
+      }
+      total = wave_sum(s);
+    }
+    return total;
+  }
+}
+
+template <typename VT>
+__device__ __forceinline__ VT load_vec(const void* p) {
+  return *(const VT*)p;
+}
+
+// ---------------------------------------------------------------------------
+// GSM / GSC + fitness partials (Algorithm 1 loop: GSM, ComputeFitness).
+// Task = (run, 512-case chunk, group of `opb` offspring).  Each wave takes
+// offspring grp*opb + wave, + waves, ...; per offspring it reads its
+// variation record, forms the chunk of the offspring row
+//   mutation:  O = S[p1] + ms * (sR[r1] - sR[r2])
+//   crossover: O = S[p1] * sR[r1] + S[p2] * (1 - sR[r1])
+// (sR holds the squashed pool semantics), stores it with non-temporal
+// 16-byte stores and writes the chunk's sum of squared residuals.  With
+// ROWS the kernel only forms the partial sums of the current population
+// (generation-0 fitness).
+template <typename T, int PREC, bool ROWS>
+__global__ __launch_bounds__(512) void k_vary(const RunDev* __restrict__ runs, Params p, VaryLaunch lc) {
+  typedef typename VecOf<T>::type VT;
+  constexpr int N = VecOf<T>::N;
+  constexpr int NJ = kChunk / (kWave * N);
+  const int lane = threadIdx.x & 63;
+  const int wave = uni(threadIdx.x >> 6);
+  int64_t L = blockIdx.x;
+  if (lc.remap) {
+    const int64_t per = lc.grid >> 3;
+    L = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  }
+  for (int64_t task = L; task < lc.total_tasks; task += lc.grid) {
+    const int run = find_run(p.n_runs, task, [&](int r) { return runs[r].vary_task0; });
+    const RunDev& R = runs[run];
+    const int64_t local = task - R.vary_task0;
+    const int chunk = (int)(local / lc.ogroups);
+    const int grp = (int)(local - (int64_t)chunk * lc.ogroups);
+    int64_t off, len;
+    if (chunk < R.nch_tr) {
+      off = (int64_t)chunk * kChunk;
+      len = R.tr_pad - off;
+    } else {
+      const int64_t cc = (int64_t)(chunk - R.nch_tr) * kChunk;
+      off = R.tr_pad + cc;
+      len = R.te_pad - cc;
+    }
+    len = len < kChunk ? len : kChunk;
+    const int gen = ROWS ? 0 : uni(R.state[kStGen]);
+    const int cur = gen & 1;
+    const int64_t ld = R.ld;
+    const T* __restrict__ Sp = (const T*)R.S[cur];
+    T* __restrict__ So = (T*)R.S[cur ^ 1];
+    const T* __restrict__ sg = (const T*)R.sigR;
+    const T* __restrict__ yv = (const T*)R.y + off;
+    int64_t e[NJ];
+    bool ok[NJ];
+    VT t[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      e[j] = (int64_t)j * kWave * N + lane * N;
+      ok[j] = e[j] < len;
+      t[j] = ok[j] ? load_vec<VT>(yv + e[j]) : VT(0);
+    }
+    int i_end = (grp + 1) * lc.opb;
+    i_end = i_end < p.m ? i_end : p.m;
+    for (int i = grp * lc.opb + wave; i < i_end; i += lc.waves) {
+      VT o[NJ];
+      if constexpr (ROWS) {
+        const T* a = Sp + (int64_t)i * ld + off;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) o[j] = ok[j] ? load_vec<VT>(a + e[j]) : VT(0);
+      } else {
+        const gsgp_record* rc = R.rec + (int64_t)gen * p.m + i;
+        const int op = uni(rc->op);
+        const int p1 = uni(rc->p1);
+        const int r1 = uni(rc->r1);
+        const T* a = Sp + (int64_t)p1 * ld + off;
+        const T* s1 = sg + (int64_t)r1 * ld + off;
+        if (op == 1) {
+          const int p2 = uni(rc->p2);
+          const T* b = Sp + (int64_t)p2 * ld + off;
+          VT va[NJ], vb[NJ], vr[NJ];
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) {
+            va[j] = ok[j] ? load_vec<VT>(a + e[j]) : VT(0);
+            vb[j] = ok[j] ? load_vec<VT>(b + e[j]) : VT(0);
+            vr[j] = ok[j] ? load_vec<VT>(s1 + e[j]) : VT(0);
+          }
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) o[j] = va[j] * vr[j] + vb[j] * ((T)1 - vr[j]);
+        } else {
+          const int r2 = uni(rc->r2);
+          const T ms = (T)rc->ms;
+          const T* s2 = sg + (int64_t)r2 * ld + off;
+          VT va[NJ], v1[NJ], v2[NJ];
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) {
+            va[j] = ok[j] ? load_vec<VT>(a + e[j]) : VT(0);
+            v1[j] = ok[j] ? load_vec<VT>(s1 + e[j]) : VT(0);
+            v2[j] = ok[j] ? load_vec<VT>(s2 + e[j]) : VT(0);
+          }
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) o[j] = va[j] + ms * (v1[j] - v2[j]);
+        }
+        if constexpr (PREC != GSGP_FP64) {
+          // a convex combination of two values near +-FLT_MAX can round past it
+#pragma unroll
+          for (int j = 0; j < NJ; ++j)
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+              const T x = o[j][c];
+              o[j][c] = x > (T)kFltMax ? (T)kFltMax : (x < (T)-kFltMax ? (T)-kFltMax : x);
+            }
+        }
+        T* dst = So + (int64_t)i * ld + off;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+          if (ok[j]) __builtin_nontemporal_store(o[j], (VT*)(dst + e[j]));
+      }
+      const double sse = chunk_sse<T, PREC, NJ, VT>(o, t, ok);
+      if (lane == 0) R.part[(int64_t)chunk * p.m + i] = sse;
+    }
+  }
+}
+
+// ComputeFitness (Section 2.2 "Fitness computation"): one wavefront per
+// (run, individual) adds its chunk sums in FP64 (lane j takes chunks j,
+// j + 64, ...; then the butterfly) and takes the root mean.
+__global__ __launch_bounds__(256) void k_fitness(const RunDev* __restrict__ runs, Params p,
+                                                 int64_t total, int init) {
+  const int lane = threadIdx.x & 63;
+  const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (gw >= total) return;
+  const int run = (int)(gw / p.m);
+  const int i = (int)(gw - (int64_t)run * p.m);
+  const RunDev& R = runs[run];
+  const int dst = init ? 0 : ((R.state[kStGen] + 1) & 1);
+  double s = 0.0;
+  for (int c = lane; c < R.nch_tr; c += kWave) s += R.part[(int64_t)c * p.m + i];
+  s = wave_sum(s);
+  double st = 0.0;
+  for (int c = R.nch_tr + lane; c < R.nch; c += kWave) st += R.part[(int64_t)c * p.m + i];
+  st = wave_sum(st);
+  if (lane == 0) {
+    R.F[dst][i] = sqrt(s / (double)R.n_train);
+    R.Ft[dst][i] = R.n_test > 0 ? sqrt(st / (double)R.n_test) : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Survival, summary and the next generation's variation draws.
+struct ValIdx {
+  double v;
+  int i;
+};
+
+__device__ __forceinline__ ValIdx pick_min(ValIdx a, ValIdx b) {
+  return (b.v < a.v || (b.v == a.v && b.i < a.i)) ? b : a;
+}
+__device__ __forceinline__ ValIdx pick_max(ValIdx a, ValIdx b) {
+  return (b.v > a.v || (b.v == a.v && b.i < a.i)) ? b : a;
+}
+
+template <bool MAX, typename View>
+__device__ ValIdx block_arg(int m, View F, ValIdx* sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  ValIdx x{MAX ? -INFINITY : INFINITY, 0x7fffffff};
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    const ValIdx y{F(i), i};
+    x = MAX ? pick_max(x, y) : pick_min(x, y);
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const ValIdx y{__shfl_xor(x.v, o, kWave), __shfl_xor(x.i, o, kWave)};
+    x = MAX ? pick_max(x, y) : pick_min(x, y);
+  }
+  if (lane == 0) sh[wave] = x;
+  __syncthreads();
+  ValIdx r = sh[0];
+  for (int w = 1; w < nw; ++w) r = MAX ? pick_max(r, sh[w]) : pick_min(r, sh[w]);
+  __syncthreads();
+  if (r.i < 0 || r.i >= m) r.i = 0;  // fitness is always finite; keep indices in range regardless
+  return r;
+}
+
+// Sequential access to the Philox words W[0], W[1], ... of one offspring:
+// word w is lane w % 4 of Philox(counter (i, w / 4, gen, 3)).
+struct WordStream {
+  uint32_t i, gen, k0, k1;
+  int block;
+  Words4 cur;
+  __device__ uint32_t at(int w) {
+    const int b = w >> 2;
+    if (b != block) {
+      cur = philox4x32_10(i, (uint32_t)b, gen, 3u, k0, k1);
+      block = b;
+    }
+    const int s = w & 3;
+    return s == 0 ? cur.w0 : (s == 1 ? cur.w1 : (s == 2 ? cur.w2 : cur.w3));
+  }
+};
+
+// Tournament: s uniform candidates, the first with strictly smaller fitness
+// wins (ties go to the earlier draw).
+template <typename View>
+__device__ __forceinline__ int32_t tournament(WordStream& ws, int first, int s, int m, View F) {
+  int32_t best = draw_below(ws.at(first), (uint32_t)m);
+  double fb = F(best);
+  for (int j = 1; j < s; ++j) {
+    const int32_t c = draw_below(ws.at(first + j), (uint32_t)m);
+    const double fc = F(c);
+    if (fc < fb) {
+      best = c;
+      fb = fc;
+    }
+  }
+  return best;
+}
+
+template <typename View>
+__device__ gsgp_record draw_record(const Params& p, uint32_t run_id, int gen_draw, int i, View F) {
+  WordStream ws{(uint32_t)i, (uint32_t)gen_draw, p.seed, run_id, -1, Words4{0, 0, 0, 0}};
+  const uint32_t w0 = ws.at(0), w1 = ws.at(1), w2 = ws.at(2), w3 = ws.at(3), w4 = ws.at(4);
+  gsgp_record rc;
+  rc.reserved = 0;
+  if (p.tsize > 0 && (uint64_t)w0 < p.t_xo) {
+    rc.op = 1;
+    rc.p1 = tournament(ws, 5, p.tsize, p.m, F);
+    rc.p2 = tournament(ws, 5 + p.tsize, p.tsize, p.m, F);
+    rc.r1 = draw_below(w1, (uint32_t)p.r);
+    rc.r2 = -1;
+    rc.ms = 0.0;
+  } else {
+    rc.op = 0;
+    rc.p1 = p.tsize > 0 ? tournament(ws, 5, p.tsize, p.m, F) : i;
+    rc.p2 = -1;
+    rc.r1 = draw_below(w1, (uint32_t)p.r);
+    rc.r2 = draw_below(w2, (uint32_t)p.r);
+    rc.ms = p.ms_random ? p.ms * draw_u53(w3, w4) : p.ms;
+  }
+  return rc;
+}
+
+// Survival with elitism (Section 2.2 "Survival"; Algorithm 1): offspring
+// replace parents; when the best parent is strictly better than the best
+// offspring it overwrites the worst offspring (lowest index on ties, as the
+// first extremum that I?AMIN / I?AMAX return).  Then the summary and the next
+// generation's draws.  surv_blks blocks per run share the elite row copy and
+// the draws; the last block to arrive publishes the elite fitness and
+// advances the generation counter.
+template <typename T>
+__global__ __launch_bounds__(256) void k_survive(const RunDev* __restrict__ runs, Params p,
+                                                 int32_t total, int mode) {
+  __shared__ ValIdx sh[8];
+  __shared__ int is_last;
+  const int run = find_run(p.n_runs, (int64_t)blockIdx.x, [&](int r) { return (int64_t)runs[r].surv_blk0; });
+  const RunDev& R = runs[run];
+  const int bl = blockIdx.x - R.surv_blk0;
+  const int nb = R.surv_blks;
+  const int m = p.m;
+  const int gen = (mode == kSurvInit) ? 0 : R.state[kStGen];
+  const int cur = gen & 1, nxt = cur ^ 1;
+  const double* FP = R.F[cur];
+  const double* FtP = R.Ft[cur];
+  double* FO = R.F[nxt];
+  double* FtO = R.Ft[nxt];
+  int copied = 0, src = -1, dst = -1;
+  int gen_draw;
+  if (mode == kSurvGen) {
+    const ValIdx bp = block_arg<false>(m, [&](int i) { return FP[i]; }, sh);
+    const ValIdx bo = block_arg<false>(m, [&](int i) { return FO[i]; }, sh);
+    const ValIdx w = block_arg<true>(m, [&](int i) { return FO[i]; }, sh);
+    if (R.state[kStReplayElite]) {
+      const gsgp_gen_stats e = R.elite_in[gen];
+      copied = e.elite_copied;
+      src = e.elite_src;
+      dst = e.elite_dst;
+    } else if (bp.v < bo.v) {
+      copied = 1;
+      src = bp.i;
+      dst = w.i;
+    }
+    if (copied) {
+      typedef typename VecOf<T>::type VT;
+      constexpr int N = VecOf<T>::N;
+      const int64_t nvec = R.ld / N;
+      const int64_t per = (nvec + nb - 1) / nb;
+      const int64_t v0 = per * bl;
+      const int64_t v1 = (v0 + per) < nvec ? (v0 + per) : nvec;
+      const VT* from = (const VT*)((const T*)R.S[cur] + (int64_t)src * R.ld);
+      VT* to = (VT*)((T*)R.S[nxt] + (int64_t)dst * R.ld);
+      for (int64_t v = v0 + threadIdx.x; v < v1; v += blockDim.x) to[v] = from[v];
+    }
+    gen_draw = gen + 2;
+  } else {
+    gen_draw = gen + 1;
+  }
+  auto view_new = [&](int i) { return (copied && i == dst) ? FP[src] : FO[i]; };
+  auto view_cur = [&](int i) { return FP[i]; };
+  if (bl == 0 && mode != kSurvSelectOnly) {
+    gsgp_gen_stats st;
+    if (mode == kSurvGen) {
+      const ValIdx b = block_arg<false>(m, view_new, sh);
+      st.best_train_rmse = b.v;
+      st.best_test_rmse = (copied && b.i == dst) ? FtP[src] : FtO[b.i];
+      st.best_index = b.i;
+    } else {
+      const ValIdx b = block_arg<false>(m, view_cur, sh);
+      st.best_train_rmse = b.v;
+      st.best_test_rmse = FtP[b.i];
+      st.best_index = b.i;
+    }
+    st.elite_copied = copied;
+    st.elite_src = src;
+    st.elite_dst = dst;
+    if (threadIdx.x == 0) R.stats[mode == kSurvGen ? gen + 1 : 0] = st;
+  }
+  if (!R.state[kStReplaySelect] && gen_draw <= p.gmax) {
+    const int per = (m + nb - 1) / nb;
+    const int i0 = per * bl;
+    const int i1 = (i0 + per) < m ? (i0 + per) : m;
+    gsgp_record* out = R.rec + (int64_t)(gen_draw - 1) * m;
+    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+      out[i] = (mode == kSurvGen) ? draw_record(p, R.run_id, gen_draw, i, view_new)
+                                  : draw_record(p, R.run_id, gen_draw, i, view_cur);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int old = atomicAdd(&R.state[kStDone], 1);
+    is_last = (old == nb - 1);
+  }
+  __syncthreads();
+  if (is_last && threadIdx.x == 0) {
+    R.state[kStDone] = 0;
+    if (mode == kSurvGen) {
+      if (copied) {
+        FO[dst] = FP[src];
+        FtO[dst] = FtP[src];
+      }
+      R.state[kStGen] = gen + 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Lineage reconstruction helpers (all FP64).
+__global__ __launch_bounds__(256) void k_transpose(const double* __restrict__ X, int64_t n, int32_t l,
+                                                   double* __restrict__ Xfm, int64_t ld) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ld) return;
+  for (int f = 0; f < l; ++f) Xfm[(int64_t)f * ld + c] = c < n ? X[c * l + f] : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_interpret_list(const int32_t* __restrict__ ops,
+                                                        const double* __restrict__ opv,
+                                                        const int32_t* __restrict__ nops, int32_t k,
+                                                        const int32_t* __restrict__ prog,
+                                                        const int32_t* __restrict__ squash,
+                                                        int32_t nprog, const double* __restrict__ Xfm,
+                                                        int64_t ld, int64_t n, double* __restrict__ out,
+                                                        int depth, int64_t total) {
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x & 63;
+  const int wave = uni(threadIdx.x >> 6);
+  const int64_t task = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+  if (task >= total) return;
+  const int64_t cb = task / nprog;
+  const int j = (int)(task - cb * nprog);
+  const int pr = uni(prog[j]);
+  int64_t col[kInterpV];
+  bool ok[kInterpV];
+#pragma unroll
+  for (int v = 0; v < kInterpV; ++v) {
+    col[v] = cb * (kWave * kInterpV) + v * kWave + lane;
+    ok[v] = col[v] < ld;
+  }
+  double val[kInterpV];
+  double* stk = lds + (int64_t)wave * depth * kInterpV * kWave;
+  eval_program<kInterpV>(ops + (int64_t)pr * k, opv + (int64_t)pr * k, uni(nops[pr]), Xfm, ld, col, ok,
+                         stk, lane, val);
+  const bool sq = squash[j] != 0;
+#pragma unroll
+  for (int v = 0; v < kInterpV; ++v) {
+    if (!ok[v]) continue;
+    double x = val[v];
+    if (sq) x = 1.0 / (1.0 + exp(-x));
+    out[(int64_t)j * ld + col[v]] = col[v] < n ? x : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_replay_nodes(const ReplayNode* __restrict__ nodes,
+                                                      const double* __restrict__ prev,
+                                                      const double* __restrict__ pool,
+                                                      double* __restrict__ next, int64_t ld, int64_t n) {
+  const ReplayNode nd = nodes[blockIdx.y];
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const double a = prev[(int64_t)nd.a * ld + c];
+  double o;
+  if (nd.op == 0) {
+    o = a + nd.ms * (pool[(int64_t)nd.r1 * ld + c] - pool[(int64_t)nd.r2 * ld + c]);
+  } else if (nd.op == 1) {
+    const double r = pool[(int64_t)nd.r1 * ld + c];
+    o = a * r + prev[(int64_t)nd.b * ld + c] * (1.0 - r);
+  } else {
+    o = a;
+  }
+  next[(int64_t)nd.out * ld + c] = o;
+}
+
+// Writes one state word of every run (generation counter, replay flags...).
+__global__ void k_set_state(const RunDev* __restrict__ runs, int32_t n_runs, int32_t word, int32_t value) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n_runs) runs[r].state[word] = value;
+}
+
+inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+// Waves per interpreter block so that the LDS stacks of one block stay
+// within 64 KiB: each wave needs depth * kInterpV * 64 doubles.
+inline int interp_waves(int depth) {
+  const int per_wave = depth * kInterpV * kWave * (int)sizeof(double);
+  int w = 65536 / per_wave;
+  return w < 1 ? 1 : (w > 4 ? 4 : w);
+}
+
+}  // namespace
+
+hipError_t launch_set_state(const RunDev* d_runs, int32_t n_runs, int32_t word, int32_t value,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_set_state, dim3(blocks_for(n_runs, 256)), dim3(256), 0, s, d_runs, n_runs, word,
+                     value);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+hipError_t launch_prep(const RunDev* d_runs, const Params& p, int64_t total_cols,
+                       const double* const* Xsrc, const double* const* /*unused*/, hipStream_t s) {
+  if (total_cols <= 0) return hipSuccess;
+  if (p.precision == GSGP_FP64)
+    hipLaunchKernelGGL(k_prep<double>, dim3(blocks_for(total_cols, 256)), dim3(256), 0, s, d_runs, p,
+                       total_cols, Xsrc);
+  else
+    hipLaunchKernelGGL(k_prep<float>, dim3(blocks_for(total_cols, 256)), dim3(256), 0, s, d_runs, p,
+                       total_cols, Xsrc);
+  return hipGetLastError();
+}
+
+hipError_t launch_genome(const RunDev* d_runs, const Params& p, hipStream_t s) {
+  const int64_t total = (int64_t)p.n_runs * (p.m + p.r) * p.k;
+  hipLaunchKernelGGL(k_genome, dim3(blocks_for(total, 256)), dim3(256), 0, s, d_runs, p, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_compile(const RunDev* d_runs, const Params& p, hipStream_t s) {
+  const int32_t total = p.n_runs * (p.m + p.r);
+  hipLaunchKernelGGL(k_compile, dim3(blocks_for(total, 256)), dim3(256), 0, s, d_runs, p, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t total_tasks, int depth,
+                            hipStream_t s) {
+  if (depth < 1) depth = 1;
+  const int waves = interp_waves(depth);
+  const size_t shmem = (size_t)waves * depth * kInterpV * kWave * sizeof(double);
+  const dim3 grid(blocks_for(total_tasks, waves));
+  if (p.precision == GSGP_FP64)
+    hipLaunchKernelGGL(k_interpret<double>, grid, dim3(waves * kWave), shmem, s, d_runs, p,
+                       total_tasks, depth);
+  else
+    hipLaunchKernelGGL(k_interpret<float>, grid, dim3(waves * kWave), shmem, s, d_runs, p,
+                       total_tasks, depth);
+  return hipGetLastError();
+}
+
+hipError_t launch_vary(const RunDev* d_runs, const Params& p, const VaryLaunch& lc, bool rows_only,
+                       hipStream_t s) {
+  if (lc.total_tasks <= 0) return hipSuccess;
+  const dim3 grid((unsigned)lc.grid), block(lc.waves * kWave);
+  switch (p.precision) {
+    case GSGP_FP64:
+      if (rows_only)
+        hipLaunchKernelGGL((k_vary<double, GSGP_FP64, true>), grid, block, 0, s, d_runs, p, lc);
+      else
+        hipLaunchKernelGGL((k_vary<double, GSGP_FP64, false>), grid, block, 0, s, d_runs, p, lc);
+      break;
+    case GSGP_FP32:
+      if (rows_only)
+        hipLaunchKernelGGL((k_vary<float, GSGP_FP32, true>), grid, block, 0, s, d_runs, p, lc);
+      else
+        hipLaunchKernelGGL((k_vary<float, GSGP_FP32, false>), grid, block, 0, s, d_runs, p, lc);
+      break;
+    default:
+      if (rows_only)
+        hipLaunchKernelGGL((k_vary<float, GSGP_FP32_KAHAN, true>), grid, block, 0, s, d_runs, p, lc);
+      else
+        hipLaunchKernelGGL((k_vary<float, GSGP_FP32_KAHAN, false>), grid, block, 0, s, d_runs, p, lc);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fitness(const RunDev* d_runs, const Params& p, bool init, hipStream_t s) {
+  const int64_t total = (int64_t)p.n_runs * p.m;
+  hipLaunchKernelGGL(k_fitness, dim3(blocks_for(total, 4)), dim3(256), 0, s, d_runs, p, total,
+                     init ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_survive(const RunDev* d_runs, const Params& p, int32_t total_blocks, int mode,
+                          hipStream_t s) {
+  if (p.precision == GSGP_FP64)
+    hipLaunchKernelGGL(k_survive<double>, dim3(total_blocks), dim3(256), 0, s, d_runs, p, total_blocks,
+                       mode);
+  else
+    hipLaunchKernelGGL(k_survive<float>, dim3(total_blocks), dim3(256), 0, s, d_runs, p, total_blocks,
+                       mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose(const double* X, int64_t n, int32_t l, double* Xfm, int64_t ld,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_transpose, dim3(blocks_for(ld, 256)), dim3(256), 0, s, X, n, l, Xfm, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_interpret_list(const int32_t* ops, const double* opv, const int32_t* nops,
+                                 int32_t k, const int32_t* prog, const int32_t* squash,
+                                 int32_t nprog, const double* Xfm, int64_t ld, int64_t n,
+                                 double* out, int depth, hipStream_t s) {
+  if (nprog <= 0) return hipSuccess;
+  if (depth < 1) depth = 1;
+  const int64_t cblocks = (ld + kWave * kInterpV - 1) / (kWave * kInterpV);
+  const int64_t total = cblocks * nprog;
+  const int waves = interp_waves(depth);
+  const size_t shmem = (size_t)waves * depth * kInterpV * kWave * sizeof(double);
+  hipLaunchKernelGGL(k_interpret_list, dim3(blocks_for(total, waves)), dim3(waves * kWave),
+                     shmem, s, ops, opv, nops, k, prog, squash, nprog, Xfm, ld, n, out, depth, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_replay_nodes(const ReplayNode* nodes, int32_t nnodes, const double* prev,
+                               const double* pool, double* next, int64_t ld, int64_t n,
+                               hipStream_t s) {
+  if (nnodes <= 0 || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_replay_nodes, dim3(blocks_for(n, 256), (unsigned)nnodes), dim3(256), 0, s, nodes,
+                     prev, pool, next, ld, n);
+  return hipGetLastError();
+}
+
+}  // namespace gsgp

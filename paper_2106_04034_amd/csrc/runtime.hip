@@ -1,0 +1,958 @@
+// Host runtime of libgsgp.so: argument validation, workspace carving,
+// launch planning, HIP graph capture of a generation, inspection and lineage
+// reconstruction.  Implements the C ABI declared in include/gsgp.h.
+//
+// Algorithm 1 of the GSGP-CUDA paper (arXiv 2106.04034) is the control flow:
+// gsgp_eval_population runs its set-up (CreatePopulation x2,
+// ComputeSemantics x2, ComputeFitness) and gsgp_generation its loop body.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+using namespace gsgp;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+gsgp_status fail(gsgp_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+inline int64_t pad_to(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+uint64_t event_threshold(double p) {
+  if (p <= 0.0) return 0;
+  if (p >= 1.0) return (uint64_t)1 << 32;
+  return (uint64_t)std::floor(p * 4294967296.0);
+}
+
+size_t storage_bytes(int32_t precision) { return precision == GSGP_FP64 ? 8 : 4; }
+
+// Byte offsets of one run's buffers inside the workspace.
+struct RunPlan {
+  int64_t n_train, n_test, tr_pad, te_pad, ld;
+  int32_t l, nch_tr, nch_te;
+  size_t X, y, S0, S1, sigR, part, F0, F1, Ft0, Ft1, rec, stats, elite_in, code, cval, ops, opv, nops;
+  size_t end;
+};
+
+struct Plan {
+  size_t runs_dev, src_ptrs, state, total;
+  std::vector<RunPlan> runs;
+};
+
+gsgp_status validate_config(const gsgp_config* c) {
+  if (!c) return fail(GSGP_ERR_ARG, "config is NULL");
+  if (c->pop_size < 1 || c->pop_size > (1 << 22)) return fail(GSGP_ERR_ARG, "pop_size %d out of [1, 2^22]", c->pop_size);
+  if (c->pool_size < 1 || c->pool_size > (1 << 22)) return fail(GSGP_ERR_ARG, "pool_size %d out of [1, 2^22]", c->pool_size);
+  if (c->genome_len < 1 || c->genome_len > 4096) return fail(GSGP_ERR_ARG, "genome_len %d out of [1, 4096]", c->genome_len);
+  if (c->n_generations_max < 1 || c->n_generations_max > (1 << 24))
+    return fail(GSGP_ERR_ARG, "n_generations_max %d out of [1, 2^24]", c->n_generations_max);
+  if (c->tournament_size < 0 || c->tournament_size > kMaxTournament)
+    return fail(GSGP_ERR_ARG, "tournament_size %d out of [0, %d]", c->tournament_size, kMaxTournament);
+  if (c->ms_random != 0 && c->ms_random != 1) return fail(GSGP_ERR_ARG, "ms_random must be 0 or 1");
+  if (!(c->p_crossover >= 0.0 && c->p_crossover <= 1.0)) return fail(GSGP_ERR_ARG, "p_crossover out of [0, 1]");
+  if (c->tournament_size == 0 && c->p_crossover != 0.0)
+    return fail(GSGP_ERR_ARG, "tournament_size 0 (mutate every individual) requires p_crossover == 0");
+  if (!(c->mutation_step >= 0.0 && c->mutation_step <= 1e6)) return fail(GSGP_ERR_ARG, "mutation_step out of [0, 1e6]");
+  if (!(c->p_function >= 0.0 && c->p_function <= 1.0) || !(c->p_feature >= 0.0 && c->p_feature <= 1.0) ||
+      !(c->p_function + c->p_feature <= 1.0 + 1e-12))
+    return fail(GSGP_ERR_ARG, "gene probabilities must lie in [0, 1] and sum to at most 1");
+  if (!std::isfinite(c->erc_lo) || !std::isfinite(c->erc_hi) || c->erc_lo > c->erc_hi ||
+      std::fabs(c->erc_lo) > 3.0e38 || std::fabs(c->erc_hi) > 3.0e38)
+    return fail(GSGP_ERR_ARG, "constant range must be finite with erc_lo <= erc_hi");
+  if (c->precision < GSGP_FP64 || c->precision > GSGP_FP32_KAHAN) return fail(GSGP_ERR_ARG, "unknown precision %d", c->precision);
+  if ((c->flags & ~GSGP_FLAG_NO_GRAPH) != 0) return fail(GSGP_ERR_ARG, "unknown flags 0x%x", c->flags);
+  if (c->reserved != 0) return fail(GSGP_ERR_ARG, "reserved config field must be 0");
+  return GSGP_OK;
+}
+
+gsgp_status make_plan(const gsgp_config* c, const gsgp_run* runs, int32_t n_runs, Plan* plan) {
+  gsgp_status st = validate_config(c);
+  if (st != GSGP_OK) return st;
+  if (!runs || n_runs < 1 || n_runs > 65536) return fail(GSGP_ERR_ARG, "need 1..65536 runs");
+  const int64_t m = c->pop_size, r = c->pool_size, k = c->genome_len, G = c->n_generations_max;
+  const size_t s = storage_bytes(c->precision);
+  size_t off = 0;
+  plan->runs_dev = off;
+  off = align_up(off + sizeof(RunDev) * n_runs);
+  plan->src_ptrs = off;
+  off = align_up(off + sizeof(double*) * 4 * n_runs);
+  plan->state = off;
+  off = align_up(off + sizeof(int32_t) * kStWords * n_runs);
+  plan->runs.resize(n_runs);
+  for (int32_t i = 0; i < n_runs; ++i) {
+    const gsgp_run& d = runs[i];
+    if (d.n_train < 1) return fail(GSGP_ERR_ARG, "run %d: n_train must be >= 1", i);
+    if (d.n_test < 0) return fail(GSGP_ERR_ARG, "run %d: n_test must be >= 0", i);
+    if (d.n_train > ((int64_t)1 << 40) || d.n_test > ((int64_t)1 << 40)) return fail(GSGP_ERR_ARG, "run %d: too many cases", i);
+    if (d.n_features < 1 || d.n_features > 65535) return fail(GSGP_ERR_ARG, "run %d: n_features out of [1, 65535]", i);
+    if (d.reserved != 0) return fail(GSGP_ERR_ARG, "run %d: reserved field must be 0", i);
+    if (!d.X_train || !d.y_train) return fail(GSGP_ERR_ARG, "run %d: NULL train data", i);
+    if ((d.n_test > 0) != (d.X_test != nullptr) || (d.n_test > 0) != (d.y_test != nullptr))
+      return fail(GSGP_ERR_ARG, "run %d: test pointers must be non-NULL iff n_test > 0", i);
+    RunPlan& p = plan->runs[i];
+    p.n_train = d.n_train;
+    p.n_test = d.n_test;
+    p.l = d.n_features;
+    p.tr_pad = pad_to(d.n_train, kSegPad);
+    p.te_pad = pad_to(d.n_test, kSegPad);
+    p.ld = p.tr_pad + p.te_pad;
+    p.nch_tr = (int32_t)((p.tr_pad + kChunk - 1) / kChunk);
+    p.nch_te = (int32_t)((p.te_pad + kChunk - 1) / kChunk);
+    auto take = [&](size_t bytes) {
+      const size_t at = off;
+      off = align_up(off + bytes);
+      return at;
+    };
+    p.X = take(sizeof(double) * p.l * p.ld);
+    p.y = take(s * p.ld);
+    p.S0 = take(s * m * p.ld);
+    p.S1 = take(s * m * p.ld);
+    p.sigR = take(s * r * p.ld);
+    p.part = take(sizeof(double) * (p.nch_tr + p.nch_te) * m);
+    p.F0 = take(8 * m);
+    p.F1 = take(8 * m);
+    p.Ft0 = take(8 * m);
+    p.Ft1 = take(8 * m);
+    p.rec = take(sizeof(gsgp_record) * G * m);
+    p.stats = take(sizeof(gsgp_gen_stats) * (G + 1));
+    p.elite_in = take(sizeof(gsgp_gen_stats) * G);
+    p.code = take(4 * (m + r) * k);
+    p.cval = take(8 * (m + r) * k);
+    p.ops = take(4 * (m + r) * k);
+    p.opv = take(8 * (m + r) * k);
+    p.nops = take(4 * (m + r));
+    p.end = off;
+  }
+  plan->total = off;
+  return GSGP_OK;
+}
+
+}  // namespace
+
+struct gsgp_handle {
+  gsgp_config cfg;
+  int32_t n_runs = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  char* ws = nullptr;
+  Plan plan;
+  std::vector<RunDev> runs_h;
+  RunDev* runs_d = nullptr;
+  Params params;
+  VaryLaunch vary{}, rows{};
+  int64_t interp_tasks = 0;
+  int32_t surv_blocks = 0;
+  int32_t depth = 1;
+  int32_t gen = 0;
+  bool evaluated = false;
+  bool poisoned = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int32_t* pinned = nullptr;  // state read-back, [n_runs][kStWords]
+  int device = 0;
+};
+
+namespace {
+
+gsgp_status hip_fail(gsgp_handle* h, hipError_t e, const char* what) {
+  if (h) h->poisoned = true;
+  return fail(GSGP_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(h, call)                                  \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return hip_fail(h, e_, #call); \
+  } while (0)
+
+gsgp_status usable(gsgp_handle* h) {
+  if (!h) return fail(GSGP_ERR_ARG, "handle is NULL");
+  if (h->poisoned) return fail(GSGP_ERR_STATE, "handle is poisoned by an earlier HIP error");
+  return GSGP_OK;
+}
+
+void drop_graph(gsgp_handle* h) {
+  if (h->exec) (void)hipGraphExecDestroy(h->exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  h->exec = nullptr;
+  h->graph = nullptr;
+}
+
+// Variation launch for the current shape.  With remap the grid is a multiple
+// of 8 so that logical blocks can be spread XCD by XCD.
+void plan_vary(gsgp_handle* h, int32_t waves, int32_t opb, int32_t remap) {
+  VaryLaunch& v = h->vary;
+  v.waves = waves;
+  v.opb = opb;
+  v.ogroups = (h->cfg.pop_size + opb - 1) / opb;
+  v.remap = remap;
+  int64_t t = 0;
+  for (int32_t i = 0; i < h->n_runs; ++i) {
+    h->runs_h[i].vary_task0 = t;
+    t += (int64_t)h->runs_h[i].nch * v.ogroups;
+  }
+  v.total_tasks = t;
+  int64_t grid = std::min<int64_t>(t, (int64_t)1 << 30);
+  if (remap) grid = pad_to(grid, 8);
+  v.grid = grid;
+}
+
+// The generation-0 partial sums use one task per (chunk, individual group)
+// with the same indexing; offspring groups of the vary plan are reused.
+void plan_rows(gsgp_handle* h) {
+  h->rows = h->vary;
+  h->rows.remap = 0;
+  h->rows.grid = h->vary.total_tasks;
+}
+
+hipError_t upload_runs(gsgp_handle* h) {
+  return hipMemcpyAsync(h->runs_d, h->runs_h.data(), sizeof(RunDev) * h->n_runs, hipMemcpyHostToDevice,
+                        h->stream);
+}
+
+hipError_t enqueue_generation(gsgp_handle* h, hipStream_t s) {
+  hipError_t e = launch_vary(h->runs_d, h->params, h->vary, false, s);
+  if (e != hipSuccess) return e;
+  e = launch_fitness(h->runs_d, h->params, false, s);
+  if (e != hipSuccess) return e;
+  return launch_survive(h->runs_d, h->params, h->surv_blocks, kSurvGen, s);
+}
+
+gsgp_status ensure_graph(gsgp_handle* h) {
+  if (h->exec) return GSGP_OK;
+  HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = enqueue_generation(h, h->cap_stream);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
+  if (e != hipSuccess) return hip_fail(h, e, "capturing a generation");
+  if (e2 != hipSuccess) return hip_fail(h, e2, "hipStreamEndCapture");
+  h->graph = g;
+  HIPCHK(h, hipGraphInstantiate(&h->exec, g, nullptr, nullptr, 0));
+  return GSGP_OK;
+}
+
+gsgp_status run_generations(gsgp_handle* h, int32_t n_gens) {
+  const bool graph = !(h->cfg.flags & GSGP_FLAG_NO_GRAPH);
+  if (graph) {
+    gsgp_status st = ensure_graph(h);
+    if (st != GSGP_OK) return st;
+    for (int32_t g = 0; g < n_gens; ++g) HIPCHK(h, hipGraphLaunch(h->exec, h->stream));
+  } else {
+    for (int32_t g = 0; g < n_gens; ++g) HIPCHK(h, enqueue_generation(h, h->stream));
+  }
+  h->gen += n_gens;
+  return GSGP_OK;
+}
+
+gsgp_status copy_stats(gsgp_handle* h, int32_t gen0, int32_t n, gsgp_gen_stats* out, int32_t stride) {
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  for (int32_t r = 0; r < h->n_runs; ++r)
+    HIPCHK(h, hipMemcpy(out + (size_t)r * stride, h->runs_h[r].stats + gen0, sizeof(gsgp_gen_stats) * n,
+                        hipMemcpyDeviceToHost));
+  return GSGP_OK;
+}
+
+gsgp_status check_run(gsgp_handle* h, int32_t run) {
+  gsgp_status st = usable(h);
+  if (st != GSGP_OK) return st;
+  if (run < 0 || run >= h->n_runs) return fail(GSGP_ERR_ARG, "run %d out of [0, %d)", run, h->n_runs);
+  if (!h->evaluated) return fail(GSGP_ERR_STATE, "gsgp_eval_population has not run");
+  return GSGP_OK;
+}
+
+template <typename T>
+void to_f64(const std::vector<char>& raw, int64_t rows, const RunDev& R, double* out) {
+  const T* s = (const T*)raw.data();
+  const int64_t n_all = R.n_train + R.n_test;
+  for (int64_t i = 0; i < rows; ++i) {
+    for (int64_t c = 0; c < R.n_train; ++c) out[i * n_all + c] = (double)s[i * R.ld + c];
+    for (int64_t c = 0; c < R.n_test; ++c) out[i * n_all + R.n_train + c] = (double)s[i * R.ld + R.tr_pad + c];
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gsgp_status_string(gsgp_status s) {
+  switch (s) {
+    case GSGP_OK: return "ok";
+    case GSGP_ERR_ARG: return "invalid argument";
+    case GSGP_ERR_STATE: return "invalid state";
+    case GSGP_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case GSGP_ERR_NONFINITE: return "non-finite input";
+    case GSGP_ERR_HIP: return "HIP error";
+    case GSGP_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* gsgp_last_error(void) { return g_last_error.c_str(); }
+
+gsgp_status gsgp_workspace_size(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_runs, size_t* bytes) {
+  if (!bytes) return fail(GSGP_ERR_ARG, "bytes is NULL");
+  Plan plan;
+  gsgp_status st = make_plan(cfg, runs, n_runs, &plan);
+  if (st != GSGP_OK) return st;
+  *bytes = plan.total;
+  return GSGP_OK;
+}
+
+gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_runs, void* d_workspace,
+                      size_t ws_bytes, void* hip_stream, gsgp_handle** out) {
+  if (!out) return fail(GSGP_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  Plan plan;
+  gsgp_status st = make_plan(cfg, runs, n_runs, &plan);
+  if (st != GSGP_OK) return st;
+  if (!d_workspace) return fail(GSGP_ERR_WORKSPACE, "workspace is NULL");
+  if (((uintptr_t)d_workspace) % kAlign) return fail(GSGP_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < plan.total)
+    return fail(GSGP_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, plan.total);
+
+  gsgp_handle* h = new gsgp_handle();
+  h->cfg = *cfg;
+  h->n_runs = n_runs;
+  h->stream = (hipStream_t)hip_stream;
+  h->ws = (char*)d_workspace;
+  h->plan = plan;
+  hipError_t e = hipGetDevice(&h->device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&h->pinned, sizeof(int32_t) * kStWords * n_runs, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    gsgp_status s2 = fail(GSGP_ERR_HIP, "creating handle resources: %s", hipGetErrorString(e));
+    gsgp_destroy(h);
+    return s2;
+  }
+  Params& p = h->params;
+  p.m = cfg->pop_size;
+  p.r = cfg->pool_size;
+  p.k = cfg->genome_len;
+  p.gmax = cfg->n_generations_max;
+  p.tsize = cfg->tournament_size;
+  p.ms_random = cfg->ms_random;
+  p.n_runs = n_runs;
+  p.precision = cfg->precision;
+  p.t_xo = event_threshold(cfg->p_crossover);
+  p.t_func = event_threshold(cfg->p_function);
+  p.t_feat = event_threshold(cfg->p_function + cfg->p_feature);
+  p.ms = cfg->mutation_step;
+  p.erc_lo = cfg->erc_lo;
+  p.erc_hi = cfg->erc_hi;
+  p.seed = cfg->seed;
+  p.pad = 0;
+
+  char* ws = h->ws;
+  h->runs_d = (RunDev*)(ws + plan.runs_dev);
+  int32_t* state = (int32_t*)(ws + plan.state);
+  h->runs_h.resize(n_runs);
+  int64_t col = 0, itask = 0;
+  int32_t sblk = 0;
+  const int rows = cfg->pop_size + cfg->pool_size;
+  for (int32_t i = 0; i < n_runs; ++i) {
+    const RunPlan& q = plan.runs[i];
+    RunDev& R = h->runs_h[i];
+    memset(&R, 0, sizeof R);
+    R.S[0] = ws + q.S0;
+    R.S[1] = ws + q.S1;
+    R.sigR = ws + q.sigR;
+    R.y = ws + q.y;
+    R.X = (double*)(ws + q.X);
+    R.part = (double*)(ws + q.part);
+    R.F[0] = (double*)(ws + q.F0);
+    R.F[1] = (double*)(ws + q.F1);
+    R.Ft[0] = (double*)(ws + q.Ft0);
+    R.Ft[1] = (double*)(ws + q.Ft1);
+    R.rec = (gsgp_record*)(ws + q.rec);
+    R.stats = (gsgp_gen_stats*)(ws + q.stats);
+    R.elite_in = (gsgp_gen_stats*)(ws + q.elite_in);
+    R.code = (int32_t*)(ws + q.code);
+    R.cval = (double*)(ws + q.cval);
+    R.ops = (int32_t*)(ws + q.ops);
+    R.opv = (double*)(ws + q.opv);
+    R.nops = (int32_t*)(ws + q.nops);
+    R.state = state + (size_t)kStWords * i;
+    R.n_train = q.n_train;
+    R.n_test = q.n_test;
+    R.tr_pad = q.tr_pad;
+    R.te_pad = q.te_pad;
+    R.ld = q.ld;
+    R.l = q.l;
+    R.nch_tr = q.nch_tr;
+    R.nch_te = q.nch_te;
+    R.nch = q.nch_tr + q.nch_te;
+    R.run_id = (uint32_t)i;
+    R.col0 = col;
+    col += q.ld;
+    R.interp_task0 = itask;
+    itask += (int64_t)rows * ((q.ld + 127) / 128);
+    R.surv_blk0 = sblk;
+    int64_t nb = (q.ld + 16383) / 16384;
+    R.surv_blks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nb, 32));
+    sblk += R.surv_blks;
+  }
+  h->interp_tasks = itask;
+  h->surv_blocks = sblk;
+  plan_vary(h, 4, 4, n_runs == 1 ? 1 : 0);
+  plan_rows(h);
+
+  std::vector<const double*> src(4 * (size_t)n_runs);
+  for (int32_t i = 0; i < n_runs; ++i) {
+    src[4 * i + 0] = runs[i].X_train;
+    src[4 * i + 1] = runs[i].y_train;
+    src[4 * i + 2] = runs[i].X_test;
+    src[4 * i + 3] = runs[i].y_test;
+  }
+  const double* const* d_src = (const double* const*)(ws + plan.src_ptrs);
+  std::vector<int32_t> zeros((size_t)kStWords * n_runs, 0);
+  e = upload_runs(h);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync((void*)d_src, src.data(), sizeof(double*) * src.size(), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(state, zeros.data(), sizeof(int32_t) * zeros.size(), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = launch_prep(h->runs_d, p, col, d_src, nullptr, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->pinned, state, sizeof(int32_t) * kStWords * n_runs, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    gsgp_status s2 = fail(GSGP_ERR_HIP, "gsgp_init: %s", hipGetErrorString(e));
+    gsgp_destroy(h);
+    return s2;
+  }
+  for (int32_t i = 0; i < n_runs; ++i) {
+    if (h->pinned[kStWords * i + kStNonFinite]) {
+      gsgp_destroy(h);
+      return fail(GSGP_ERR_NONFINITE, "run %d: X or y holds NaN/Inf (or |y| > FLT_MAX)", i);
+    }
+  }
+  *out = h;
+  return GSGP_OK;
+}
+
+gsgp_status gsgp_destroy(gsgp_handle* h) {
+  if (!h) return GSGP_OK;
+  drop_graph(h);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  if (h->pinned) (void)hipHostFree(h->pinned);
+  delete h;
+  return GSGP_OK;
+}
+
+gsgp_status gsgp_eval_population(gsgp_handle* h, const int32_t* h_codes, const double* h_consts) {
+  gsgp_status st = usable(h);
+  if (st != GSGP_OK) return st;
+  if ((h_codes == nullptr) != (h_consts == nullptr)) return fail(GSGP_ERR_ARG, "give both codes and constants, or neither");
+  const Params& p = h->params;
+  const int64_t per = (int64_t)(p.m + p.r) * p.k;
+  if (h_codes) {
+    for (int32_t r = 0; r < h->n_runs; ++r) {
+      const int32_t l = h->runs_h[r].l;
+      for (int64_t q = 0; q < per; ++q) {
+        const int32_t c = h_codes[r * per + q];
+        if (c < -5 || c >= l) return fail(GSGP_ERR_ARG, "run %d gene %lld: code %d out of [-5, %d)", r, (long long)q, c, l);
+        if (!std::isfinite(h_consts[r * per + q])) return fail(GSGP_ERR_ARG, "run %d gene %lld: constant not finite", r, (long long)q);
+      }
+    }
+  }
+  for (int32_t w : {kStGen, kStDone, kStReplaySelect, kStReplayElite, kStMaxDepth})
+    HIPCHK(h, launch_set_state(h->runs_d, h->n_runs, w, 0, h->stream));
+  if (h_codes) {
+    for (int32_t r = 0; r < h->n_runs; ++r) {
+      HIPCHK(h, hipMemcpyAsync(h->runs_h[r].code, h_codes + r * per, 4 * per, hipMemcpyHostToDevice, h->stream));
+      HIPCHK(h, hipMemcpyAsync(h->runs_h[r].cval, h_consts + r * per, 8 * per, hipMemcpyHostToDevice, h->stream));
+    }
+  } else {
+    HIPCHK(h, launch_genome(h->runs_d, p, h->stream));
+  }
+  HIPCHK(h, launch_compile(h->runs_d, p, h->stream));
+  const RunPlan& q0 = h->plan.runs[0];
+  (void)q0;
+  int32_t* state = (int32_t*)(h->ws + h->plan.state);
+  HIPCHK(h, hipMemcpyAsync(h->pinned, state, sizeof(int32_t) * kStWords * h->n_runs, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  int32_t deepest = 0;
+  for (int32_t r = 0; r < h->n_runs; ++r) deepest = std::max(deepest, h->pinned[kStWords * r + kStMaxDepth]);
+  if (deepest > kMaxStack) {
+    h->evaluated = false;
+    return fail(GSGP_ERR_UNSUPPORTED, "a genome needs a stack of %d values; at most %d are supported", deepest, kMaxStack);
+  }
+  h->depth = std::max(1, deepest - 1);
+  HIPCHK(h, launch_interpret(h->runs_d, p, h->interp_tasks, h->depth, h->stream));
+  HIPCHK(h, launch_vary(h->runs_d, p, h->rows, true, h->stream));
+  HIPCHK(h, launch_fitness(h->runs_d, p, true, h->stream));
+  HIPCHK(h, launch_survive(h->runs_d, p, h->surv_blocks, kSurvInit, h->stream));
+  h->gen = 0;
+  h->evaluated = true;
+  return GSGP_OK;
+}
+
+gsgp_status gsgp_generation(gsgp_handle* h, int32_t n_gens, gsgp_gen_stats* h_stats) {
+  gsgp_status st = usable(h);
+  if (st != GSGP_OK) return st;
+  if (!h->evaluated) return fail(GSGP_ERR_STATE, "gsgp_eval_population has not run");
+  if (n_gens < 1) return fail(GSGP_ERR_ARG, "n_gens must be >= 1");
+  if ((int64_t)h->gen + n_gens > h->cfg.n_generations_max)
+    return fail(GSGP_ERR_ARG, "generation %d + %d exceeds n_generations_max %d", h->gen, n_gens, h->cfg.n_generations_max);
+  const int32_t g0 = h->gen;
+  st = run_generations(h, n_gens);
+  if (st != GSGP_OK) return st;
+  if (h_stats) return copy_stats(h, g0 + 1, n_gens, h_stats, n_gens);
+  return GSGP_OK;
+}
+
+gsgp_status gsgp_generation_replay(gsgp_handle* h, int32_t n_gens, const gsgp_record* h_records,
+                                   const gsgp_gen_stats* h_elite, gsgp_gen_stats* h_stats) {
+  gsgp_status st = usable(h);
+  if (st != GSGP_OK) return st;
+  if (!h->evaluated) return fail(GSGP_ERR_STATE, "gsgp_eval_population has not run");
+  if (n_gens < 1 || !h_records) return fail(GSGP_ERR_ARG, "need n_gens >= 1 and records");
+  if ((int64_t)h->gen + n_gens > h->cfg.n_generations_max)
+    return fail(GSGP_ERR_ARG, "generation %d + %d exceeds n_generations_max %d", h->gen, n_gens, h->cfg.n_generations_max);
+  const int32_t m = h->cfg.pop_size, r = h->cfg.pool_size;
+  for (int64_t q = 0; q < (int64_t)h->n_runs * n_gens * m; ++q) {
+    const gsgp_record& d = h_records[q];
+    const bool ok = (d.op == 0 && d.p1 >= 0 && d.p1 < m && d.r1 >= 0 && d.r1 < r && d.r2 >= 0 && d.r2 < r &&
+                     std::isfinite(d.ms)) ||
+                    (d.op == 1 && d.p1 >= 0 && d.p1 < m && d.p2 >= 0 && d.p2 < m && d.r1 >= 0 && d.r1 < r);
+    if (!ok) return fail(GSGP_ERR_ARG, "record %lld is not a valid mutation or crossover", (long long)q);
+  }
+  if (h_elite) {
+    for (int64_t q = 0; q < (int64_t)h->n_runs * n_gens; ++q) {
+      const gsgp_gen_stats& e = h_elite[q];
+      if (e.elite_copied != 0 && e.elite_copied != 1) return fail(GSGP_ERR_ARG, "elite decision %lld: elite_copied must be 0/1", (long long)q);
+      if (e.elite_copied && (e.elite_src < 0 || e.elite_src >= m || e.elite_dst < 0 || e.elite_dst >= m))
+        return fail(GSGP_ERR_ARG, "elite decision %lld: index out of range", (long long)q);
+    }
+  }
+  const int32_t g0 = h->gen;
+  for (int32_t run = 0; run < h->n_runs; ++run) {
+    HIPCHK(h, hipMemcpyAsync(h->runs_h[run].rec + (int64_t)g0 * m, h_records + (int64_t)run * n_gens * m,
+                             sizeof(gsgp_record) * n_gens * m, hipMemcpyHostToDevice, h->stream));
+    if (h_elite)
+      HIPCHK(h, hipMemcpyAsync(h->runs_h[run].elite_in + g0, h_elite + (int64_t)run * n_gens,
+                               sizeof(gsgp_gen_stats) * n_gens, hipMemcpyHostToDevice, h->stream));
+  }
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  HIPCHK(h, launch_set_state(h->runs_d, h->n_runs, kStReplaySelect, 1, h->stream));
+  HIPCHK(h, launch_set_state(h->runs_d, h->n_runs, kStReplayElite, h_elite ? 1 : 0, h->stream));
+  st = run_generations(h, n_gens);
+  if (st != GSGP_OK) return st;
+  HIPCHK(h, launch_set_state(h->runs_d, h->n_runs, kStReplaySelect, 0, h->stream));
+  HIPCHK(h, launch_set_state(h->runs_d, h->n_runs, kStReplayElite, 0, h->stream));
+  HIPCHK(h, launch_survive(h->runs_d, h->params, h->surv_blocks, kSurvSelectOnly, h->stream));
+  if (h_stats) return copy_stats(h, g0 + 1, n_gens, h_stats, n_gens);
+  return GSGP_OK;
+}
+
+gsgp_status gsgp_current_generation(gsgp_handle* h, int32_t* gen) {
+  gsgp_status st = usable(h);
+  if (st != GSGP_OK) return st;
+  if (!gen) return fail(GSGP_ERR_ARG, "gen is NULL");
+  *gen = h->gen;
+  return GSGP_OK;
+}
+
+gsgp_status gsgp_get_fitness(gsgp_handle* h, int32_t run, double* h_train, double* h_test) {
+  gsgp_status st = check_run(h, run);
+  if (st != GSGP_OK) return st;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  const RunDev& R = h->runs_h[run];
+  const int cur = h->gen & 1;
+  if (h_train) HIPCHK(h, hipMemcpy(h_train, R.F[cur], 8 * h->cfg.pop_size, hipMemcpyDeviceToHost));
+  if (h_test) HIPCHK(h, hipMemcpy(h_test, R.Ft[cur], 8 * h->cfg.pop_size, hipMemcpyDeviceToHost));
+  return GSGP_OK;
+}
+
+gsgp_status gsgp_get_semantics(gsgp_handle* h, int32_t run, int32_t which, double* h_out) {
+  gsgp_status st = check_run(h, run);
+  if (st != GSGP_OK) return st;
+  if (which != 0 && which != 1) return fail(GSGP_ERR_ARG, "which must be 0 (population) or 1 (pool)");
+  if (!h_out) return fail(GSGP_ERR_ARG, "h_out is NULL");
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  const RunDev& R = h->runs_h[run];
+  const int64_t rows = which == 0 ? h->cfg.pop_size : h->cfg.pool_size;
+  const size_t s = storage_bytes(h->cfg.precision);
+  std::vector<char> raw((size_t)rows * R.ld * s);
+  const void* from = which == 0 ? R.S[h->gen & 1] : R.sigR;
+  HIPCHK(h, hipMemcpy(raw.data(), from, raw.size(), hipMemcpyDeviceToHost));
+  if (s == 8)
+    to_f64<double>(raw, rows, R, h_out);
+  else
+    to_f64<float>(raw, rows, R, h_out);
+  return GSGP_OK;
+}
+
+gsgp_status gsgp_get_records(gsgp_handle* h, int32_t run, int32_t gen0, int32_t n_gens, int32_t raw,
+                             gsgp_record* h_out) {
+  gsgp_status st = check_run(h, run);
+  if (st != GSGP_OK) return st;
+  if (!h_out || n_gens < 1 || gen0 < 1 || (int64_t)gen0 + n_gens - 1 > h->gen)
+    return fail(GSGP_ERR_ARG, "records of generations %d..%d are not available (current %d)", gen0, gen0 + n_gens - 1, h->gen);
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  const int32_t m = h->cfg.pop_size;
+  const RunDev& R = h->runs_h[run];
+  HIPCHK(h, hipMemcpy(h_out, R.rec + (int64_t)(gen0 - 1) * m, sizeof(gsgp_record) * n_gens * m, hipMemcpyDeviceToHost));
+  if (!raw) {
+    std::vector<gsgp_gen_stats> s(n_gens);
+    HIPCHK(h, hipMemcpy(s.data(), R.stats + gen0, sizeof(gsgp_gen_stats) * n_gens, hipMemcpyDeviceToHost));
+    for (int32_t g = 0; g < n_gens; ++g) {
+      if (!s[g].elite_copied) continue;
+      gsgp_record& d = h_out[(int64_t)g * m + s[g].elite_dst];
+      d = gsgp_record{2, s[g].elite_src, -1, -1, -1, 0, 0.0};
+    }
+  }
+  return GSGP_OK;
+}
+
+gsgp_status gsgp_get_stats(gsgp_handle* h, int32_t run, int32_t gen0, int32_t n_gens, gsgp_gen_stats* h_out) {
+  gsgp_status st = check_run(h, run);
+  if (st != GSGP_OK) return st;
+  if (!h_out || n_gens < 1 || gen0 < 0 || (int64_t)gen0 + n_gens - 1 > h->gen)
+    return fail(GSGP_ERR_ARG, "summaries of generations %d..%d are not available (current %d)", gen0, gen0 + n_gens - 1, h->gen);
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  HIPCHK(h, hipMemcpy(h_out, h->runs_h[run].stats + gen0, sizeof(gsgp_gen_stats) * n_gens, hipMemcpyDeviceToHost));
+  return GSGP_OK;
+}
+
+gsgp_status gsgp_get_genomes(gsgp_handle* h, int32_t run, int32_t* h_codes, double* h_consts) {
+  gsgp_status st = check_run(h, run);
+  if (st != GSGP_OK) return st;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  const int64_t per = (int64_t)(h->cfg.pop_size + h->cfg.pool_size) * h->cfg.genome_len;
+  if (h_codes) HIPCHK(h, hipMemcpy(h_codes, h->runs_h[run].code, 4 * per, hipMemcpyDeviceToHost));
+  if (h_consts) HIPCHK(h, hipMemcpy(h_consts, h->runs_h[run].cval, 8 * per, hipMemcpyDeviceToHost));
+  return GSGP_OK;
+}
+
+gsgp_status gsgp_time_stages(gsgp_handle* h, int32_t n_gens, double* h_ms) {
+  gsgp_status st = usable(h);
+  if (st != GSGP_OK) return st;
+  if (!h->evaluated) return fail(GSGP_ERR_STATE, "gsgp_eval_population has not run");
+  if (!h_ms || n_gens < 1) return fail(GSGP_ERR_ARG, "need n_gens >= 1 and an output array");
+  if ((int64_t)h->gen + n_gens > h->cfg.n_generations_max)
+    return fail(GSGP_ERR_ARG, "generation %d + %d exceeds n_generations_max %d", h->gen, n_gens, h->cfg.n_generations_max);
+  std::vector<hipEvent_t> ev((size_t)4 * n_gens, nullptr);
+  gsgp_status result = GSGP_OK;
+  for (auto& e : ev) {
+    hipError_t x = hipEventCreate(&e);
+    if (x != hipSuccess) {
+      result = hip_fail(h, x, "hipEventCreate");
+      break;
+    }
+  }
+  double acc[4] = {0, 0, 0, 0};
+  if (result == GSGP_OK) {
+    for (int32_t g = 0; g < n_gens && result == GSGP_OK; ++g) {
+      hipEvent_t* e = &ev[(size_t)4 * g];
+      hipError_t x = hipEventRecord(e[0], h->stream);
+      if (x == hipSuccess) x = launch_vary(h->runs_d, h->params, h->vary, false, h->stream);
+      if (x == hipSuccess) x = hipEventRecord(e[1], h->stream);
+      if (x == hipSuccess) x = launch_fitness(h->runs_d, h->params, false, h->stream);
+      if (x == hipSuccess) x = hipEventRecord(e[2], h->stream);
+      if (x == hipSuccess) x = launch_survive(h->runs_d, h->params, h->surv_blocks, kSurvGen, h->stream);
+      if (x == hipSuccess) x = hipEventRecord(e[3], h->stream);
+      if (x != hipSuccess) result = hip_fail(h, x, "timed generation");
+    }
+    if (result == GSGP_OK) {
+      h->gen += n_gens;
+      hipError_t x = hipStreamSynchronize(h->stream);
+      if (x != hipSuccess) result = hip_fail(h, x, "hipStreamSynchronize");
+    }
+    for (int32_t g = 0; g < n_gens && result == GSGP_OK; ++g) {
+      hipEvent_t* e = &ev[(size_t)4 * g];
+      float a = 0, b = 0, c = 0, d = 0;
+      hipError_t x = hipEventElapsedTime(&a, e[0], e[1]);
+      if (x == hipSuccess) x = hipEventElapsedTime(&b, e[1], e[2]);
+      if (x == hipSuccess) x = hipEventElapsedTime(&c, e[2], e[3]);
+      if (x == hipSuccess) x = hipEventElapsedTime(&d, e[0], e[3]);
+      if (x != hipSuccess) {
+        result = hip_fail(h, x, "hipEventElapsedTime");
+        break;
+      }
+      acc[0] += c;
+      acc[1] += a;
+      acc[2] += b;
+      acc[3] += d;
+    }
+  }
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (result == GSGP_OK)
+    for (int i = 0; i < 4; ++i) h_ms[i] = acc[i] / n_gens;
+  return result;
+}
+
+gsgp_status gsgp_set_launch(gsgp_handle* h, int32_t waves_per_block, int32_t offspring_per_block, int32_t xcd_remap) {
+  gsgp_status st = usable(h);
+  if (st != GSGP_OK) return st;
+  const int32_t w = waves_per_block ? waves_per_block : h->vary.waves;
+  const int32_t o = offspring_per_block ? offspring_per_block : h->vary.opb;
+  if (w < 1 || w > 8) return fail(GSGP_ERR_ARG, "waves_per_block must be in [1, 8]");
+  if (o < 1 || o > 4096) return fail(GSGP_ERR_ARG, "offspring_per_block must be in [1, 4096]");
+  if (xcd_remap != 0 && xcd_remap != 1) return fail(GSGP_ERR_ARG, "xcd_remap must be 0 or 1");
+  plan_vary(h, w, o, xcd_remap);
+  plan_rows(h);
+  HIPCHK(h, upload_runs(h));
+  drop_graph(h);
+  return GSGP_OK;
+}
+
+gsgp_status gsgp_autotune(gsgp_handle* h, int32_t* h_best) {
+  gsgp_status st = usable(h);
+  if (st != GSGP_OK) return st;
+  if (!h->evaluated) return fail(GSGP_ERR_STATE, "gsgp_eval_population has not run");
+  // The variation kernel is idempotent for a fixed generation (it reads the
+  // parents and writes the offspring buffer), so shapes can be timed on the
+  // live buffers without advancing the run.
+  const VaryLaunch keep = h->vary;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  int32_t best[3] = {keep.waves, keep.opb, keep.remap};
+  const int32_t wave_opts[] = {2, 4, 8};
+  const int32_t opb_mult[] = {1, 2, 4, 8};
+  gsgp_status result = GSGP_OK;
+  for (int32_t w : wave_opts) {
+    for (int32_t mult : opb_mult) {
+      for (int32_t remap = 0; remap <= 1 && result == GSGP_OK; ++remap) {
+        plan_vary(h, w, w * mult, remap);
+        hipError_t x = upload_runs(h);
+        for (int rep = 0; rep < 2 && x == hipSuccess; ++rep) x = launch_vary(h->runs_d, h->params, h->vary, false, h->stream);
+        if (x == hipSuccess) x = hipEventRecord(e0, h->stream);
+        for (int rep = 0; rep < 5 && x == hipSuccess; ++rep) x = launch_vary(h->runs_d, h->params, h->vary, false, h->stream);
+        if (x == hipSuccess) x = hipEventRecord(e1, h->stream);
+        if (x == hipSuccess) x = hipEventSynchronize(e1);
+        float ms = 0;
+        if (x == hipSuccess) x = hipEventElapsedTime(&ms, e0, e1);
+        if (x != hipSuccess) {
+          result = hip_fail(h, x, "autotune trial");
+          break;
+        }
+        if (ms < best_ms) {
+          best_ms = ms;
+          best[0] = w;
+          best[1] = w * mult;
+          best[2] = remap;
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (result != GSGP_OK) return result;
+  plan_vary(h, best[0], best[1], best[2]);
+  plan_rows(h);
+  HIPCHK(h, upload_runs(h));
+  drop_graph(h);
+  if (h_best) memcpy(h_best, best, sizeof best);
+  return GSGP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Lineage reconstruction.
+namespace {
+
+struct Lineage {
+  std::vector<std::vector<int32_t>> need;  // need[g]: individuals of generation g, sorted
+  std::vector<int32_t> pool;               // pool trees used, sorted
+  std::vector<gsgp_record> rec;            // [gen][m]
+  std::vector<gsgp_gen_stats> stats;       // [gen + 1]
+  size_t max_slots = 1, total_nodes = 0;
+  int64_t ld = 0;
+  size_t off_X = 0, off_pool = 0, off_A = 0, off_B = 0, off_prog = 0, off_nodes = 0, total = 0;
+};
+
+gsgp_status walk_lineage(gsgp_handle* h, int32_t run, int32_t gen, int32_t individual, int64_t n, Lineage* L) {
+  const int32_t m = h->cfg.pop_size;
+  const RunDev& R = h->runs_h[run];
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  L->rec.resize((size_t)gen * m);
+  L->stats.resize((size_t)gen + 1);
+  if (gen > 0) {
+    HIPCHK(h, hipMemcpy(L->rec.data(), R.rec, sizeof(gsgp_record) * gen * m, hipMemcpyDeviceToHost));
+    HIPCHK(h, hipMemcpy(L->stats.data(), R.stats, sizeof(gsgp_gen_stats) * (gen + 1), hipMemcpyDeviceToHost));
+  }
+  std::vector<std::set<int32_t>> need(gen + 1);
+  std::set<int32_t> pool;
+  need[gen].insert(individual);
+  for (int32_t g = gen; g >= 1; --g) {
+    const gsgp_gen_stats& s = L->stats[g];
+    for (int32_t i : need[g]) {
+      if (s.elite_copied && i == s.elite_dst) {
+        need[g - 1].insert(s.elite_src);
+        continue;
+      }
+      const gsgp_record& d = L->rec[(size_t)(g - 1) * m + i];
+      need[g - 1].insert(d.p1);
+      pool.insert(d.r1);
+      if (d.op == 1)
+        need[g - 1].insert(d.p2);
+      else
+        pool.insert(d.r2);
+    }
+  }
+  L->need.resize(gen + 1);
+  L->max_slots = 1;
+  L->total_nodes = 0;
+  for (int32_t g = 0; g <= gen; ++g) {
+    L->need[g].assign(need[g].begin(), need[g].end());
+    L->max_slots = std::max(L->max_slots, L->need[g].size());
+    if (g > 0) L->total_nodes += L->need[g].size();
+  }
+  L->pool.assign(pool.begin(), pool.end());
+  L->ld = pad_to(n, kSegPad);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  L->off_X = take(sizeof(double) * R.l * L->ld);
+  L->off_pool = take(sizeof(double) * std::max<size_t>(1, L->pool.size()) * L->ld);
+  L->off_A = take(sizeof(double) * L->max_slots * L->ld);
+  L->off_B = take(sizeof(double) * L->max_slots * L->ld);
+  L->off_prog = take(sizeof(int32_t) * 2 * (L->need[0].size() + L->pool.size() + 2));
+  L->off_nodes = take(sizeof(ReplayNode) * std::max<size_t>(1, L->total_nodes));
+  L->total = off;
+  return GSGP_OK;
+}
+
+}  // namespace
+
+gsgp_status gsgp_reconstruct_scratch_size(gsgp_handle* h, int32_t run, int32_t gen, int32_t individual, int64_t n,
+                                          size_t* bytes) {
+  gsgp_status st = check_run(h, run);
+  if (st != GSGP_OK) return st;
+  if (!bytes) return fail(GSGP_ERR_ARG, "bytes is NULL");
+  if (gen < 0 || gen > h->gen) return fail(GSGP_ERR_ARG, "generation %d not in [0, %d]", gen, h->gen);
+  if (individual < 0 || individual >= h->cfg.pop_size) return fail(GSGP_ERR_ARG, "individual out of range");
+  if (n < 1 || n > ((int64_t)1 << 40)) return fail(GSGP_ERR_ARG, "n must be >= 1");
+  Lineage L;
+  st = walk_lineage(h, run, gen, individual, n, &L);
+  if (st != GSGP_OK) return st;
+  *bytes = L.total;
+  return GSGP_OK;
+}
+
+gsgp_status gsgp_reconstruct(gsgp_handle* h, int32_t run, int32_t gen, int32_t individual, const double* d_X,
+                             int64_t n, double* d_out, void* d_scratch, size_t scratch_bytes) {
+  gsgp_status st = check_run(h, run);
+  if (st != GSGP_OK) return st;
+  if (gen < 0 || gen > h->gen) return fail(GSGP_ERR_ARG, "generation %d not in [0, %d]", gen, h->gen);
+  if (individual < 0 || individual >= h->cfg.pop_size) return fail(GSGP_ERR_ARG, "individual out of range");
+  if (n < 1 || n > ((int64_t)1 << 40)) return fail(GSGP_ERR_ARG, "n must be >= 1");
+  if (!d_X || !d_out) return fail(GSGP_ERR_ARG, "NULL data or output pointer");
+  if (!d_scratch || ((uintptr_t)d_scratch) % kAlign) return fail(GSGP_ERR_WORKSPACE, "scratch must be non-NULL and 256-byte aligned");
+  Lineage L;
+  st = walk_lineage(h, run, gen, individual, n, &L);
+  if (st != GSGP_OK) return st;
+  if (scratch_bytes < L.total) return fail(GSGP_ERR_WORKSPACE, "scratch has %zu bytes, needs %zu", scratch_bytes, L.total);
+  const RunDev& R = h->runs_h[run];
+  const int32_t m = h->cfg.pop_size;
+  char* sc = (char*)d_scratch;
+  double* Xfm = (double*)(sc + L.off_X);
+  double* pool = (double*)(sc + L.off_pool);
+  double* bufA = (double*)(sc + L.off_A);
+  double* bufB = (double*)(sc + L.off_B);
+  int32_t* prog = (int32_t*)(sc + L.off_prog);
+  ReplayNode* nodes = (ReplayNode*)(sc + L.off_nodes);
+
+  // host-side lists: generation-0 programs, pool programs, replay nodes
+  const size_t n0 = L.need[0].size(), np = L.pool.size();
+  std::vector<int32_t> lists(2 * (n0 + np + 2), 0);
+  int32_t* prog0 = lists.data();
+  int32_t* sq0 = prog0 + n0 + 1;
+  int32_t* progp = sq0 + n0 + 1;
+  int32_t* sqp = progp + np + 1;
+  for (size_t j = 0; j < n0; ++j) prog0[j] = L.need[0][j];
+  for (size_t j = 0; j < np; ++j) {
+    progp[j] = m + L.pool[j];
+    sqp[j] = 1;
+  }
+  std::map<int32_t, int32_t> pool_slot;
+  for (size_t j = 0; j < np; ++j) pool_slot[L.pool[j]] = (int32_t)j;
+  std::vector<ReplayNode> all_nodes;
+  all_nodes.reserve(L.total_nodes);
+  std::vector<size_t> node_begin(gen + 2, 0);
+  for (int32_t g = 1; g <= gen; ++g) {
+    node_begin[g] = all_nodes.size();
+    std::map<int32_t, int32_t> prev_slot;
+    for (size_t j = 0; j < L.need[g - 1].size(); ++j) prev_slot[L.need[g - 1][j]] = (int32_t)j;
+    const gsgp_gen_stats& s = L.stats[g];
+    for (size_t j = 0; j < L.need[g].size(); ++j) {
+      const int32_t i = L.need[g][j];
+      ReplayNode nd{};
+      nd.out = (int32_t)j;
+      nd.b = -1;
+      nd.r1 = -1;
+      nd.r2 = -1;
+      nd.ms = 0.0;
+      if (s.elite_copied && i == s.elite_dst) {
+        nd.op = 2;
+        nd.a = prev_slot.at(s.elite_src);
+      } else {
+        const gsgp_record& d = L.rec[(size_t)(g - 1) * m + i];
+        nd.op = d.op;
+        nd.a = prev_slot.at(d.p1);
+        nd.r1 = pool_slot.at(d.r1);
+        if (d.op == 1) {
+          nd.b = prev_slot.at(d.p2);
+        } else {
+          nd.r2 = pool_slot.at(d.r2);
+          nd.ms = d.ms;
+        }
+      }
+      all_nodes.push_back(nd);
+    }
+  }
+  node_begin[gen + 1] = all_nodes.size();
+  HIPCHK(h, hipMemcpyAsync(prog, lists.data(), sizeof(int32_t) * lists.size(), hipMemcpyHostToDevice, h->stream));
+  if (!all_nodes.empty())
+    HIPCHK(h, hipMemcpyAsync(nodes, all_nodes.data(), sizeof(ReplayNode) * all_nodes.size(), hipMemcpyHostToDevice,
+                             h->stream));
+  const int32_t* d_prog0 = prog;
+  const int32_t* d_sq0 = prog + n0 + 1;
+  const int32_t* d_progp = d_sq0 + n0 + 1;
+  const int32_t* d_sqp = d_progp + np + 1;
+  HIPCHK(h, launch_transpose(d_X, n, R.l, Xfm, L.ld, h->stream));
+  HIPCHK(h, launch_interpret_list(R.ops, R.opv, R.nops, h->cfg.genome_len, d_prog0, d_sq0, (int32_t)n0, Xfm, L.ld, n,
+                                  bufA, h->depth, h->stream));
+  HIPCHK(h, launch_interpret_list(R.ops, R.opv, R.nops, h->cfg.genome_len, d_progp, d_sqp, (int32_t)np, Xfm, L.ld, n,
+                                  pool, h->depth, h->stream));
+  double* cur = bufA;
+  double* nxt = bufB;
+  for (int32_t g = 1; g <= gen; ++g) {
+    const size_t b = node_begin[g], e = node_begin[g + 1];
+    HIPCHK(h, launch_replay_nodes(nodes + b, (int32_t)(e - b), cur, pool, nxt, L.ld, n, h->stream));
+    std::swap(cur, nxt);
+  }
+  const auto& last = L.need[gen];
+  const int32_t slot = (int32_t)(std::lower_bound(last.begin(), last.end(), individual) - last.begin());
+  HIPCHK(h, hipMemcpyAsync(d_out, cur + (int64_t)slot * L.ld, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return GSGP_OK;
+}
+
+}  // extern "C"
