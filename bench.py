@@ -114,7 +114,8 @@ def main() -> int:
     ap.add_argument("--generations", type=int, default=0,
                     help="override the workload's generation count (profiling runs only)")
     ap.add_argument("--launch", default="",
-                    help="variation launch shape waves,offspring_per_block,xcd_remap (skips autotuning)")
+                    help="variation launch shape waves,offspring_per_block,xcd_remap,max_blocks "
+                         "(skips autotuning)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -145,9 +146,9 @@ def main() -> int:
 
     R.eval_population()
     if args.launch:
-        w, o, x = (int(v) for v in args.launch.split(","))
-        R.set_launch(w, o, x)
-        tuned = {"waves": w, "offspring_per_block": o, "xcd_remap": x}
+        w, o, x, g = (int(v) for v in args.launch.split(","))
+        R.set_launch(w, o, x, g)
+        tuned = {"waves": w, "offspring_per_block": o, "xcd_remap": x, "max_blocks": g}
     else:
         tuned = None if args.no_autotune else R.autotune()
 
@@ -178,7 +179,8 @@ def main() -> int:
     ng = min(args.stage_gens, G)
     stages = R.time_stages(ng)
     rec = R.records(0, 1, ng)
-    n_chunks = -(-(-(-wl.n_train // 64) * 64) // 512) + -(-(-(-wl.n_test // 64) * 64) // 512)
+    chunk = 4096 // s_bytes  # canonical chunk: 4 KiB of a semantic row
+    n_chunks = -(-(-(-wl.n_train // 64) * 64) // chunk) + -(-(-(-wl.n_test // 64) * 64) // chunk)
     per_launch = float(np.mean([vary_bytes(rec[g], n_all, s_bytes, m, n_chunks) for g in range(ng)]))
     u = np.array([distinct_rows(rec[g]) for g in range(ng)])
     achieved = per_launch / (stages["vary_ms"] * 1e-3) / 1e9

@@ -53,7 +53,7 @@ typedef enum {
  * form; the FP32 forms round semantics once when they are stored.
  *   GSGP_FP64        : FP64 semantics, FP64 arithmetic.
  *   GSGP_FP32        : FP32 semantics and arithmetic, plain FP32 sums of
- *                      squared residuals within each 512-case chunk.
+ *                      squared residuals within each 1,024-case chunk.
  *   GSGP_FP32_KAHAN  : as GSGP_FP32 with compensated (Kahan / two-sum)
  *                      chunk sums.
  * Chunk sums are combined in FP64 in a fixed order in every form. */
@@ -229,15 +229,20 @@ gsgp_status gsgp_get_genomes(gsgp_handle* h, int32_t run, int32_t* h_codes, doub
  * fitness combination, and the whole generation.  Advances the runs. */
 gsgp_status gsgp_time_stages(gsgp_handle* h, int32_t n_gens, double* h_ms);
 
-/* Launch shape of the variation kernel: waves per block and offspring per
- * block; 0 keeps the current value.  Shapes never change results: partial
- * sums follow a fixed chunking of the cases.  Errors: GSGP_ERR_ARG. */
+/* Launch shape of the variation kernel: waves per block (1..8) and
+ * offspring per block task (0 keeps the current value for either), XCD-aware
+ * block order (0 none; 1 each XCD takes a contiguous range of tasks; 2 the
+ * XCDs take neighbouring case chunks side by side), and max_blocks (0 = one block per task; > 0 = a
+ * persistent grid of at most that many blocks looping over tasks).  Shapes
+ * never change results: partial sums follow a fixed chunking of the cases.
+ * Errors: GSGP_ERR_ARG. */
 gsgp_status gsgp_set_launch(gsgp_handle* h, int32_t waves_per_block, int32_t offspring_per_block,
-                            int32_t xcd_remap);
+                            int32_t xcd_remap, int32_t max_blocks);
 
 /* Times candidate launch shapes of the variation kernel on the live buffers
- * (advancing the runs by a few generations) and keeps the fastest.  h_best
- * (HOST, nullable) receives {waves_per_block, offspring_per_block, xcd_remap}.
+ * (the kernel is idempotent within a generation, so the runs do not
+ * advance) and keeps the fastest.  h_best (HOST, nullable) receives
+ * {waves_per_block, offspring_per_block, xcd_remap, max_blocks}.
  * Errors: GSGP_ERR_STATE, GSGP_ERR_HIP. */
 gsgp_status gsgp_autotune(gsgp_handle* h, int32_t* h_best);
 

@@ -12,8 +12,12 @@ namespace gsgp {
 // Canonical case chunk: fitness partial sums are formed over these runs of
 // consecutive cases of one segment (train or test), in a fixed order, and
 // combined in FP64 in chunk order.  Launch shapes never change the chunking,
-// so fitness bits (and therefore selection) do not depend on tuning.
-constexpr int kChunk = 512;
+// so fitness bits (and therefore selection) do not depend on tuning.  A
+// chunk is 4 KiB of one semantic row (1,024 FP32 or 512 FP64 cases): each
+// offspring task then reads and writes 4 KiB contiguous per row, which keeps
+// HBM efficient under the random row order of the operators.
+constexpr int kChunkBytes = 4096;
+constexpr int chunk_cases(int storage_bytes) { return kChunkBytes / storage_bytes; }
 // Each segment (train, test) of a semantic row is padded with zeros to a
 // multiple of this many cases; rows therefore start 256-byte aligned.
 constexpr int kSegPad = 64;
@@ -79,6 +83,43 @@ struct Params {
   uint32_t seed;
   int32_t pad;
 };
+
+// Chunk-tiled layout of every semantic buffer (population, pool): the
+// padded columns of a run are cut into chunks (train segment first, then
+// test), and each chunk stores the slices of all rows one after another.
+// Element (row i, column col) of a buffer with `rows` rows lives at
+//   rows * cs + i * len + (col - cs)
+// where cs and len are the first column and the length of col's chunk.  One
+// chunk's parents, pool trees and offspring thus sit in three contiguous
+// blocks, which keeps address translation and DRAM pages local while the
+// operators pick rows at random.
+struct ChunkGeom {
+  int64_t cs;   // first padded column of the chunk
+  int64_t len;  // columns in the chunk (a multiple of kSegPad)
+};
+
+__host__ __device__ inline ChunkGeom chunk_geom(int64_t tr_pad, int64_t te_pad, int32_t nch_tr, int32_t c,
+                                                int64_t chunk) {
+  ChunkGeom g;
+  if (c < nch_tr) {
+    g.cs = (int64_t)c * chunk;
+    g.len = tr_pad - g.cs;
+  } else {
+    const int64_t k = (int64_t)(c - nch_tr) * chunk;
+    g.cs = tr_pad + k;
+    g.len = te_pad - k;
+  }
+  if (g.len > chunk) g.len = chunk;
+  return g;
+}
+
+// Index of (row i, padded column col) in a chunk-tiled buffer of `rows` rows.
+__host__ __device__ inline int64_t tiled_index(int64_t tr_pad, int64_t te_pad, int32_t nch_tr, int64_t chunk,
+                                               int64_t rows, int64_t i, int64_t col) {
+  const int32_t c = col < tr_pad ? (int32_t)(col / chunk) : nch_tr + (int32_t)((col - tr_pad) / chunk);
+  const ChunkGeom g = chunk_geom(tr_pad, te_pad, nch_tr, c, chunk);
+  return rows * g.cs + i * g.len + (col - g.cs);
+}
 
 // Launch shape of the variation kernel.
 struct VaryLaunch {

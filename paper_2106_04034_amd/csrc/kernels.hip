@@ -14,13 +14,13 @@
 //                program is wave-uniform (no divergence), lanes own cases,
 //                the top of stack lives in registers and the rest of the
 //                stack in a lane-strided LDS column;
-//   k_vary       the hot loop: every offspring row of one 512-case chunk is
+//   k_vary       the hot loop: every offspring row of one 4 KiB case chunk is
 //                formed from its parent and pool rows with 16-byte loads and
 //                non-temporal 16-byte stores, and the chunk's squared
 //                residual sum is reduced across the wave with xor shuffles;
 //                blocks on one XCD share a chunk so distinct parent and pool
 //                rows are fetched from HBM about once per chunk;
-//   k_fitness    one wavefront per offspring combines chunk sums in FP64;
+//   k_fitness    lanes own individuals and waves own chunk ranges; FP64 sums;
 //   k_survive    argmin / argmax with lowest-index ties, elite row copy,
 //                per-generation summary and the next generation's tournaments.
 // All kernels are compiled without floating-point contraction so that the
@@ -317,15 +317,18 @@ __global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ ru
   double* stk = lds + (int64_t)wave * depth * kInterpV * kWave;
   eval_program<kInterpV>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k,
                          uni(R.nops[prog]), R.X, ld, col, ok, stk, lane, out);
-  T* dst = prog < p.m ? (T*)R.S[0] + (int64_t)prog * ld : (T*)R.sigR + (int64_t)(prog - p.m) * ld;
+  const bool pool = prog >= p.m;
+  T* dst = pool ? (T*)R.sigR : (T*)R.S[0];
+  const int64_t nrows = pool ? p.r : p.m;
+  const int64_t row = pool ? prog - p.m : prog;
 #pragma unroll
   for (int v = 0; v < kInterpV; ++v) {
     if (!ok[v]) continue;
     const int64_t c = col[v];
     const bool real = c < R.n_train || (c >= R.tr_pad && c < R.tr_pad + R.n_test);
     double val = out[v];
-    if (prog >= p.m) val = 1.0 / (1.0 + exp(-val));
-    dst[c] = real ? (T)val : (T)0;
+    if (pool) val = 1.0 / (1.0 + exp(-val));
+    dst[tiled_index(R.tr_pad, R.te_pad, R.nch_tr, chunk_cases(sizeof(T)), nrows, row, c)] = real ? (T)val : (T)0;
   }
 }
 
@@ -361,9 +364,12 @@ __device__ __forceinline__ void wave_sum_kahan(float& s, float& c) {
 
 // Sum over one chunk of (o - t)^2 in the canonical order: each lane adds its
 // elements in address order, then the wave butterfly.  FP32 forms fall back
-// to FP64 when a square overflows.
+// to FP64 when a square overflows; the fallback re-reads the chunk of the
+// row (`row`, already stored by this wave) and of the target (`tgt`) so the
+// offspring values need not stay live across the reduction.
 template <typename T, int PREC, int NJ, typename VT>
-__device__ __forceinline__ double chunk_sse(const VT (&o)[NJ], const VT (&t)[NJ], const bool (&ok)[NJ]) {
+__device__ __forceinline__ double chunk_sse(const VT (&o)[NJ], const VT (&t)[NJ], const bool (&ok)[NJ],
+                                            const T* row, const T* tgt, int lane) {
   constexpr int N = VecOf<T>::N;
   if constexpr (PREC == GSGP_FP64) {
     double s = 0.0;
@@ -410,14 +416,17 @@ __device__ __forceinline__ double chunk_sse(const VT (&o)[NJ], const VT (&t)[NJ]
       total = (double)s - (double)comp;
     }
     if (!isfinite(total)) {
+      // make this wave's own stores of the row visible to its loads
+      __atomic_thread_fence(__ATOMIC_SEQ_CST);
       double s = 0.0;
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         if (!ok[j]) continue;
+        const int e = j * kWave * N + lane * N;
 #pragma unroll
         for (int c = 0; c < N; ++c) {
-          const double e = (double)o[j][c] - (double)t[j][c];
-          s += e * e;
+          const double d = (double)__builtin_nontemporal_load(row + e + c) - (double)tgt[e + c];
+          s += d * d;
         }
       }
       total = wave_sum(s);
@@ -426,15 +435,154 @@ __device__ __forceinline__ double chunk_sse(const VT (&o)[NJ], const VT (&t)[NJ]
   }
 }
 
+// Buffers reach the kernels through RunDev as generic pointers; casting to
+// the global address space lets the compiler emit global (not flat) memory
+// instructions, and the constant address space gives scalar loads for data
+// no kernel in flight writes (records, generation counter).
+#define GSGP_GLOBAL __attribute__((address_space(1)))
+#define GSGP_CONST __attribute__((address_space(4)))
+
 template <typename VT>
-__device__ __forceinline__ VT load_vec(const void* p) {
-  return *(const VT*)p;
+__device__ __forceinline__ VT gload(const void* p) {
+  return *(const GSGP_GLOBAL VT*)p;
+}
+
+template <typename VT>
+__device__ __forceinline__ void gstore_nt(const VT& v, void* p) {
+  __builtin_nontemporal_store(v, (GSGP_GLOBAL VT*)p);
+}
+
+template <typename X>
+__device__ __forceinline__ X cload(const X* p) {
+  return *(const GSGP_CONST X*)p;
+}
+
+// One offspring's operands for one chunk.  Mutation reads S[p1], sR[r1],
+// sR[r2]; crossover reads S[p1], S[p2], sR[r1].  The pointer choice is
+// wave-uniform, so both kinds issue the same three 16-byte loads per slot.
+// FULL chunks need no lane masks (only a segment's last chunk can be short).
+template <typename T, int PREC, bool FULL, int NJ>
+__device__ __forceinline__ void vary_offspring(const gsgp_record* rc, const T* Sc, const T* gc, T* dst,
+                                               int lane, int64_t len,
+                                               const typename VecOf<T>::type (&t)[NJ], const T* tgt,
+                                               double* part_out) {
+  typedef typename VecOf<T>::type VT;
+  constexpr int N = VecOf<T>::N;
+  constexpr int64_t kChunk = chunk_cases(sizeof(T));
+  // row stride inside a chunk block is the chunk length (compile-time for full chunks)
+  const int64_t stride = FULL ? kChunk : len;
+  const int op = uni(cload(&rc->op));
+  const int p1 = uni(cload(&rc->p1));
+  const int r1 = uni(cload(&rc->r1));
+  const int second = uni(op == 1 ? cload(&rc->p2) : cload(&rc->r2));
+  const T ms = (T)cload(&rc->ms);
+  const T* A = Sc + (int64_t)p1 * stride;
+  const T* B = (op == 1 ? Sc : gc) + (int64_t)(op == 1 ? second : r1) * stride;
+  const T* C = gc + (int64_t)(op == 1 ? r1 : second) * stride;
+  bool ok[NJ];
+  VT x[NJ], y[NJ], z[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int e = j * kWave * N + lane * N;
+    ok[j] = FULL || e < len;
+    if (ok[j]) {
+      x[j] = gload<VT>(A + e);
+      y[j] = gload<VT>(B + e);
+      z[j] = gload<VT>(C + e);
+    } else {
+      x[j] = VT(0);
+      y[j] = VT(0);
+      z[j] = VT(0);
+    }
+  }
+  VT o[NJ];
+  if (op == 1) {
+    // GSC: O = S[p1] * sR[r1] + S[p2] * (1 - sR[r1])
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) o[j] = x[j] * z[j] + y[j] * ((T)1 - z[j]);
+  } else {
+    // GSM: O = S[p1] + ms * (sR[r1] - sR[r2])
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) o[j] = x[j] + ms * (y[j] - z[j]);
+  }
+  if constexpr (PREC != GSGP_FP64) {
+    // a convex combination of two values near +-FLT_MAX can round past it
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        const T v = o[j][c];
+        o[j][c] = v > (T)kFltMax ? (T)kFltMax : (v < (T)-kFltMax ? (T)-kFltMax : v);
+      }
+  }
+#pragma unroll
+  for (int j = 0; j < NJ; ++j)
+    if (ok[j]) gstore_nt<VT>(o[j], dst + j * kWave * N + lane * N);
+  const double sse = chunk_sse<T, PREC, NJ, VT>(o, t, ok, dst, tgt, lane);
+  if (lane == 0) *part_out = sse;
+}
+
+// Partial sums of an existing row (generation-0 fitness).
+template <typename T, int PREC, bool FULL, int NJ>
+__device__ __forceinline__ void row_partial(const T* row, int lane, int64_t len,
+                                            const typename VecOf<T>::type (&t)[NJ], const T* tgt,
+                                            double* part_out) {
+  typedef typename VecOf<T>::type VT;
+  constexpr int N = VecOf<T>::N;
+  bool ok[NJ];
+  VT o[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int e = j * kWave * N + lane * N;
+    ok[j] = FULL || e < len;
+    o[j] = ok[j] ? gload<VT>(row + e) : VT(0);
+  }
+  const double sse = chunk_sse<T, PREC, NJ, VT>(o, t, ok, row, tgt, lane);
+  if (lane == 0) *part_out = sse;
+}
+
+template <typename T, int PREC, bool ROWS, bool FULL>
+__device__ __forceinline__ void vary_task(const RunDev& R, const Params& p, const VaryLaunch& lc, int chunk,
+                                          int grp, int lane, int wave) {
+  typedef typename VecOf<T>::type VT;
+  constexpr int N = VecOf<T>::N;
+  constexpr int kChunk = chunk_cases(sizeof(T));
+  constexpr int NJ = kChunk / (kWave * N);
+  // each instance derives the chunk geometry itself from the chunk index
+  const ChunkGeom g = chunk_geom(R.tr_pad, R.te_pad, R.nch_tr, chunk, kChunk);
+  const int64_t cs = g.cs;
+  const int64_t len = FULL ? (int64_t)kChunk : g.len;
+  const int gen = ROWS ? 0 : uni(cload(&R.state[kStGen]));
+  const int cur = gen & 1;
+  // chunk blocks of the tiled buffers (see chunk_geom): rows * cs elements in
+  const T* Sc = (const T*)R.S[cur] + (int64_t)p.m * cs;
+  T* Oc = (T*)R.S[cur ^ 1] + (int64_t)p.m * cs;
+  const T* gc = (const T*)R.sigR + (int64_t)p.r * cs;
+  const T* yv = (const T*)R.y + cs;
+  const int64_t stride = FULL ? (int64_t)chunk_cases(sizeof(T)) : len;
+  VT t[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int e = j * kWave * N + lane * N;
+    t[j] = (FULL || e < len) ? gload<VT>(yv + e) : VT(0);
+  }
+  int i_end = (grp + 1) * lc.opb;
+  i_end = i_end < p.m ? i_end : p.m;
+  double* part = R.part + (int64_t)chunk * p.m;
+  if constexpr (ROWS) {
+    for (int i = grp * lc.opb + wave; i < i_end; i += lc.waves)
+      row_partial<T, PREC, FULL, NJ>(Sc + (int64_t)i * stride, lane, len, t, yv, part + i);
+  } else {
+    const gsgp_record* recs = R.rec + (int64_t)gen * p.m;
+    for (int i = grp * lc.opb + wave; i < i_end; i += lc.waves)
+      vary_offspring<T, PREC, FULL, NJ>(recs + i, Sc, gc, Oc + (int64_t)i * stride, lane, len, t, yv, part + i);
+  }
 }
 
 // ---------------------------------------------------------------------------
 // GSM / GSC + fitness partials (Algorithm 1 loop: GSM, ComputeFitness).
-// Task = (run, 512-case chunk, group of `opb` offspring).  Each wave takes
-// offspring grp*opb + wave, + waves, ...; per offspring it reads its
+// Task = (run, 4 KiB chunk of cases, group of `opb` offspring).  Each wave
+// takes offspring grp*opb + wave, + waves, ...; per offspring it reads its
 // variation record, forms the chunk of the offspring row
 //   mutation:  O = S[p1] + ms * (sR[r1] - sR[r2])
 //   crossover: O = S[p1] * sR[r1] + S[p2] * (1 - sR[r1])
@@ -444,129 +592,86 @@ __device__ __forceinline__ VT load_vec(const void* p) {
 // (generation-0 fitness).
 template <typename T, int PREC, bool ROWS>
 __global__ __launch_bounds__(512) void k_vary(const RunDev* __restrict__ runs, Params p, VaryLaunch lc) {
-  typedef typename VecOf<T>::type VT;
-  constexpr int N = VecOf<T>::N;
-  constexpr int NJ = kChunk / (kWave * N);
+  constexpr int kChunk = chunk_cases(sizeof(T));
   const int lane = threadIdx.x & 63;
   const int wave = uni(threadIdx.x >> 6);
-  int64_t L = blockIdx.x;
-  if (lc.remap) {
-    const int64_t per = lc.grid >> 3;
-    L = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  }
-  for (int64_t task = L; task < lc.total_tasks; task += lc.grid) {
+  // Hardware dispatch sends block b to XCD b % 8.  remap 1: each XCD takes a
+  // contiguous range of tasks.  remap 2: XCD x takes the x-th group of
+  // `ogroups` tasks (one chunk) of every run of 8 chunks, so the XCDs sweep
+  // the rows side by side through an 8-chunk window.
+  const int64_t xcd = blockIdx.x & 7, slot = blockIdx.x >> 3, per = lc.grid >> 3;
+  for (int64_t it = 0;; ++it) {
+    int64_t task;
+    if (lc.remap == 2) {
+      const int64_t q = slot + it * per;
+      task = (q / lc.ogroups) * 8 * lc.ogroups + xcd * lc.ogroups + q % lc.ogroups;
+      if ((q / lc.ogroups) * 8 * lc.ogroups >= lc.total_tasks) break;
+      if (task >= lc.total_tasks) continue;
+    } else {
+      task = (lc.remap ? xcd * per + slot : (int64_t)blockIdx.x) + it * lc.grid;
+      if (task >= lc.total_tasks) break;
+    }
     const int run = find_run(p.n_runs, task, [&](int r) { return runs[r].vary_task0; });
     const RunDev& R = runs[run];
     const int64_t local = task - R.vary_task0;
     const int chunk = (int)(local / lc.ogroups);
     const int grp = (int)(local - (int64_t)chunk * lc.ogroups);
-    int64_t off, len;
-    if (chunk < R.nch_tr) {
-      off = (int64_t)chunk * kChunk;
-      len = R.tr_pad - off;
-    } else {
-      const int64_t cc = (int64_t)(chunk - R.nch_tr) * kChunk;
-      off = R.tr_pad + cc;
-      len = R.te_pad - cc;
-    }
-    len = len < kChunk ? len : kChunk;
-    const int gen = ROWS ? 0 : uni(R.state[kStGen]);
-    const int cur = gen & 1;
-    const int64_t ld = R.ld;
-    const T* __restrict__ Sp = (const T*)R.S[cur];
-    T* __restrict__ So = (T*)R.S[cur ^ 1];
-    const T* __restrict__ sg = (const T*)R.sigR;
-    const T* __restrict__ yv = (const T*)R.y + off;
-    int64_t e[NJ];
-    bool ok[NJ];
-    VT t[NJ];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      e[j] = (int64_t)j * kWave * N + lane * N;
-      ok[j] = e[j] < len;
-      t[j] = ok[j] ? load_vec<VT>(yv + e[j]) : VT(0);
-    }
-    int i_end = (grp + 1) * lc.opb;
-    i_end = i_end < p.m ? i_end : p.m;
-    for (int i = grp * lc.opb + wave; i < i_end; i += lc.waves) {
-      VT o[NJ];
-      if constexpr (ROWS) {
-        const T* a = Sp + (int64_t)i * ld + off;
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) o[j] = ok[j] ? load_vec<VT>(a + e[j]) : VT(0);
-      } else {
-        const gsgp_record* rc = R.rec + (int64_t)gen * p.m + i;
-        const int op = uni(rc->op);
-        const int p1 = uni(rc->p1);
-        const int r1 = uni(rc->r1);
-        const T* a = Sp + (int64_t)p1 * ld + off;
-        const T* s1 = sg + (int64_t)r1 * ld + off;
-        if (op == 1) {
-          const int p2 = uni(rc->p2);
-          const T* b = Sp + (int64_t)p2 * ld + off;
-          VT va[NJ], vb[NJ], vr[NJ];
-#pragma unroll
-          for (int j = 0; j < NJ; ++j) {
-            va[j] = ok[j] ? load_vec<VT>(a + e[j]) : VT(0);
-            vb[j] = ok[j] ? load_vec<VT>(b + e[j]) : VT(0);
-            vr[j] = ok[j] ? load_vec<VT>(s1 + e[j]) : VT(0);
-          }
-#pragma unroll
-          for (int j = 0; j < NJ; ++j) o[j] = va[j] * vr[j] + vb[j] * ((T)1 - vr[j]);
-        } else {
-          const int r2 = uni(rc->r2);
-          const T ms = (T)rc->ms;
-          const T* s2 = sg + (int64_t)r2 * ld + off;
-          VT va[NJ], v1[NJ], v2[NJ];
-#pragma unroll
-          for (int j = 0; j < NJ; ++j) {
-            va[j] = ok[j] ? load_vec<VT>(a + e[j]) : VT(0);
-            v1[j] = ok[j] ? load_vec<VT>(s1 + e[j]) : VT(0);
-            v2[j] = ok[j] ? load_vec<VT>(s2 + e[j]) : VT(0);
-          }
-#pragma unroll
-          for (int j = 0; j < NJ; ++j) o[j] = va[j] + ms * (v1[j] - v2[j]);
-        }
-        if constexpr (PREC != GSGP_FP64) {
-          // a convex combination of two values near +-FLT_MAX can round past it
-#pragma unroll
-          for (int j = 0; j < NJ; ++j)
-#pragma unroll
-            for (int c = 0; c < N; ++c) {
-              const T x = o[j][c];
-              o[j][c] = x > (T)kFltMax ? (T)kFltMax : (x < (T)-kFltMax ? (T)-kFltMax : x);
-            }
-        }
-        T* dst = So + (int64_t)i * ld + off;
-#pragma unroll
-        for (int j = 0; j < NJ; ++j)
-          if (ok[j]) __builtin_nontemporal_store(o[j], (VT*)(dst + e[j]));
-      }
-      const double sse = chunk_sse<T, PREC, NJ, VT>(o, t, ok);
-      if (lane == 0) R.part[(int64_t)chunk * p.m + i] = sse;
-    }
+    const ChunkGeom g = chunk_geom(R.tr_pad, R.te_pad, R.nch_tr, chunk, kChunk);
+    if (g.len == kChunk)
+      vary_task<T, PREC, ROWS, true>(R, p, lc, chunk, grp, lane, wave);
+    else
+      vary_task<T, PREC, ROWS, false>(R, p, lc, chunk, grp, lane, wave);
   }
 }
 
-// ComputeFitness (Section 2.2 "Fitness computation"): one wavefront per
-// (run, individual) adds its chunk sums in FP64 (lane j takes chunks j,
-// j + 64, ...; then the butterfly) and takes the root mean.
-__global__ __launch_bounds__(256) void k_fitness(const RunDev* __restrict__ runs, Params p,
-                                                 int64_t total, int init) {
-  const int lane = threadIdx.x & 63;
-  const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (gw >= total) return;
-  const int run = (int)(gw / p.m);
-  const int i = (int)(gw - (int64_t)run * p.m);
-  const RunDev& R = runs[run];
-  const int dst = init ? 0 : ((R.state[kStGen] + 1) & 1);
+// ComputeFitness (Section 2.2 "Fitness computation"): a block takes 64
+// individuals of one run (lane = individual, so the chunk-major partial sums
+// are read with coalesced loads); its kFitWaves waves split each segment's
+// chunks into contiguous ranges, sum them in chunk order, and the ranges are
+// added in wave order in FP64.  Then the root mean.
+constexpr int kFitWaves = 16;
+
+__device__ __forceinline__ double sum_range(const double* __restrict__ part, int64_t m, int i, int c0, int c1) {
   double s = 0.0;
-  for (int c = lane; c < R.nch_tr; c += kWave) s += R.part[(int64_t)c * p.m + i];
-  s = wave_sum(s);
-  double st = 0.0;
-  for (int c = R.nch_tr + lane; c < R.nch; c += kWave) st += R.part[(int64_t)c * p.m + i];
-  st = wave_sum(st);
-  if (lane == 0) {
+  int c = c0;
+  for (; c + 4 <= c1; c += 4) {
+    const double a = part[(int64_t)c * m + i];
+    const double b = part[(int64_t)(c + 1) * m + i];
+    const double d = part[(int64_t)(c + 2) * m + i];
+    const double e = part[(int64_t)(c + 3) * m + i];
+    s += a;
+    s += b;
+    s += d;
+    s += e;
+  }
+  for (; c < c1; ++c) s += part[(int64_t)c * m + i];
+  return s;
+}
+
+__global__ __launch_bounds__(kFitWaves * 64) void k_fitness(const RunDev* __restrict__ runs, Params p,
+                                                             int32_t blocks_per_run, int init) {
+  __shared__ double sh_tr[kFitWaves][kWave];
+  __shared__ double sh_te[kFitWaves][kWave];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int run = blockIdx.x / blocks_per_run;
+  const int i = (blockIdx.x - run * blocks_per_run) * kWave + lane;
+  const RunDev& R = runs[run];
+  const bool live = i < p.m;
+  const int ii = live ? i : 0;
+  const int nt = R.nch_tr, ne = R.nch - R.nch_tr;
+  const int a0 = (int)((int64_t)nt * wave / kFitWaves), a1 = (int)((int64_t)nt * (wave + 1) / kFitWaves);
+  const int b0 = nt + (int)((int64_t)ne * wave / kFitWaves), b1 = nt + (int)((int64_t)ne * (wave + 1) / kFitWaves);
+  sh_tr[wave][lane] = sum_range(R.part, p.m, ii, a0, a1);
+  sh_te[wave][lane] = sum_range(R.part, p.m, ii, b0, b1);
+  __syncthreads();
+  if (wave == 0 && live) {
+    double s = sh_tr[0][lane], st = sh_te[0][lane];
+    for (int w = 1; w < kFitWaves; ++w) {
+      s += sh_tr[w][lane];
+      st += sh_te[w][lane];
+    }
+    const int dst = init ? 0 : ((R.state[kStGen] + 1) & 1);
     R.F[dst][i] = sqrt(s / (double)R.n_train);
     R.Ft[dst][i] = R.n_test > 0 ? sqrt(st / (double)R.n_test) : 0.0;
   }
@@ -666,17 +771,60 @@ __device__ gsgp_record draw_record(const Params& p, uint32_t run_id, int gen_dra
   return rc;
 }
 
+// Block-wide reduction of three extrema in one pass: argmin of a, argmin of
+// b, argmax of b (lowest index on ties).
+template <typename A, typename B>
+__device__ void block_arg3(int m, A fa, B fb, ValIdx* sh, ValIdx& min_a, ValIdx& min_b, ValIdx& max_b) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  ValIdx x{INFINITY, 0x7fffffff}, y{INFINITY, 0x7fffffff}, z{-INFINITY, 0x7fffffff};
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    const double va = fa(i), vb = fb(i);
+    x = pick_min(x, ValIdx{va, i});
+    y = pick_min(y, ValIdx{vb, i});
+    z = pick_max(z, ValIdx{vb, i});
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    x = pick_min(x, ValIdx{__shfl_xor(x.v, o, kWave), __shfl_xor(x.i, o, kWave)});
+    y = pick_min(y, ValIdx{__shfl_xor(y.v, o, kWave), __shfl_xor(y.i, o, kWave)});
+    z = pick_max(z, ValIdx{__shfl_xor(z.v, o, kWave), __shfl_xor(z.i, o, kWave)});
+  }
+  if (lane == 0) {
+    sh[wave] = x;
+    sh[8 + wave] = y;
+    sh[16 + wave] = z;
+  }
+  __syncthreads();
+  min_a = sh[0];
+  min_b = sh[8];
+  max_b = sh[16];
+  for (int w = 1; w < nw; ++w) {
+    min_a = pick_min(min_a, sh[w]);
+    min_b = pick_min(min_b, sh[8 + w]);
+    max_b = pick_max(max_b, sh[16 + w]);
+  }
+  __syncthreads();
+  // fitness is always finite; keep indices in range regardless
+  if (min_a.i < 0 || min_a.i >= m) min_a.i = 0;
+  if (min_b.i < 0 || min_b.i >= m) min_b.i = 0;
+  if (max_b.i < 0 || max_b.i >= m) max_b.i = 0;
+}
+
+constexpr int kSurvLdsMaxM = 4096;  // parents + offspring fitness staged in LDS up to this m
+
 // Survival with elitism (Section 2.2 "Survival"; Algorithm 1): offspring
 // replace parents; when the best parent is strictly better than the best
 // offspring it overwrites the worst offspring (lowest index on ties, as the
 // first extremum that I?AMIN / I?AMAX return).  Then the summary and the next
 // generation's draws.  surv_blks blocks per run share the elite row copy and
-// the draws; the last block to arrive publishes the elite fitness and
-// advances the generation counter.
-template <typename T>
+// the draws; each block stages the fitness arrays in LDS (LDS = true) and
+// takes the survival decision redundantly; the last block to arrive
+// publishes the elite fitness and advances the generation counter.
+template <typename T, bool LDS>
 __global__ __launch_bounds__(256) void k_survive(const RunDev* __restrict__ runs, Params p,
                                                  int32_t total, int mode) {
-  __shared__ ValIdx sh[8];
+  extern __shared__ double fit[];  // [2 m] when LDS: parents, then offspring
+  __shared__ ValIdx sh[24];
   __shared__ int is_last;
   const int run = find_run(p.n_runs, (int64_t)blockIdx.x, [&](int r) { return (int64_t)runs[r].surv_blk0; });
   const RunDev& R = runs[run];
@@ -684,18 +832,28 @@ __global__ __launch_bounds__(256) void k_survive(const RunDev* __restrict__ runs
   const int nb = R.surv_blks;
   const int m = p.m;
   const int gen = (mode == kSurvInit) ? 0 : R.state[kStGen];
+  const int replay_elite = R.state[kStReplayElite];
+  const int replay_select = R.state[kStReplaySelect];
   const int cur = gen & 1, nxt = cur ^ 1;
   const double* FP = R.F[cur];
   const double* FtP = R.Ft[cur];
   double* FO = R.F[nxt];
   double* FtO = R.Ft[nxt];
+  const bool gen_mode = mode == kSurvGen;
+  if constexpr (LDS) {
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+      fit[i] = FP[i];
+      if (gen_mode) fit[m + i] = FO[i];
+    }
+    __syncthreads();
+  }
+  const double* fP = LDS ? fit : FP;
+  const double* fO = LDS ? fit + m : FO;
   int copied = 0, src = -1, dst = -1;
-  int gen_draw;
-  if (mode == kSurvGen) {
-    const ValIdx bp = block_arg<false>(m, [&](int i) { return FP[i]; }, sh);
-    const ValIdx bo = block_arg<false>(m, [&](int i) { return FO[i]; }, sh);
-    const ValIdx w = block_arg<true>(m, [&](int i) { return FO[i]; }, sh);
-    if (R.state[kStReplayElite]) {
+  ValIdx bp, bo, wo;
+  block_arg3(m, [&](int i) { return fP[i]; }, [&](int i) { return gen_mode ? fO[i] : fP[i]; }, sh, bp, bo, wo);
+  if (gen_mode) {
+    if (replay_elite) {
       const gsgp_gen_stats e = R.elite_in[gen];
       copied = e.elite_copied;
       src = e.elite_src;
@@ -703,51 +861,74 @@ __global__ __launch_bounds__(256) void k_survive(const RunDev* __restrict__ runs
     } else if (bp.v < bo.v) {
       copied = 1;
       src = bp.i;
-      dst = w.i;
+      dst = wo.i;
     }
     if (copied) {
       typedef typename VecOf<T>::type VT;
       constexpr int N = VecOf<T>::N;
+      constexpr int64_t CH = chunk_cases(sizeof(T));
       const int64_t nvec = R.ld / N;
       const int64_t per = (nvec + nb - 1) / nb;
       const int64_t v0 = per * bl;
       const int64_t v1 = (v0 + per) < nvec ? (v0 + per) : nvec;
-      const VT* from = (const VT*)((const T*)R.S[cur] + (int64_t)src * R.ld);
-      VT* to = (VT*)((T*)R.S[nxt] + (int64_t)dst * R.ld);
-      for (int64_t v = v0 + threadIdx.x; v < v1; v += blockDim.x) to[v] = from[v];
+      const T* from = (const T*)R.S[cur];
+      T* to = (T*)R.S[nxt];
+      // four vectors in flight per thread; all N cases of a vector lie in one chunk
+      constexpr int U = 4;
+      const int64_t step = (int64_t)blockDim.x * U;
+      for (int64_t v = v0 + threadIdx.x; v < v1; v += step) {
+        VT buf[U];
+        int64_t at[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t w = v + (int64_t)u * blockDim.x;
+          if (w < v1) {
+            const int64_t col = w * N;
+            buf[u] = *(const VT*)(from + tiled_index(R.tr_pad, R.te_pad, R.nch_tr, CH, m, src, col));
+            at[u] = tiled_index(R.tr_pad, R.te_pad, R.nch_tr, CH, m, dst, col);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (v + (int64_t)u * blockDim.x < v1) *(VT*)(to + at[u]) = buf[u];
+      }
     }
-    gen_draw = gen + 2;
-  } else {
-    gen_draw = gen + 1;
   }
-  auto view_new = [&](int i) { return (copied && i == dst) ? FP[src] : FO[i]; };
-  auto view_cur = [&](int i) { return FP[i]; };
+  // fitness of the individuals the next draw selects from
+  auto view_new = [&](int i) { return (copied && i == dst) ? fP[src] : fO[i]; };
+  auto view_cur = [&](int i) { return fP[i]; };
   if (bl == 0 && mode != kSurvSelectOnly) {
-    gsgp_gen_stats st;
-    if (mode == kSurvGen) {
-      const ValIdx b = block_arg<false>(m, view_new, sh);
-      st.best_train_rmse = b.v;
-      st.best_test_rmse = (copied && b.i == dst) ? FtP[src] : FtO[b.i];
-      st.best_index = b.i;
+    ValIdx b;
+    if (gen_mode) {
+      if (replay_elite) {
+        b = block_arg<false>(m, view_new, sh);
+      } else {
+        // an elite copy is strictly better than every offspring
+        b = copied ? ValIdx{fP[src], dst} : bo;
+      }
     } else {
-      const ValIdx b = block_arg<false>(m, view_cur, sh);
-      st.best_train_rmse = b.v;
-      st.best_test_rmse = FtP[b.i];
-      st.best_index = b.i;
+      b = bp;
     }
-    st.elite_copied = copied;
-    st.elite_src = src;
-    st.elite_dst = dst;
-    if (threadIdx.x == 0) R.stats[mode == kSurvGen ? gen + 1 : 0] = st;
+    if (threadIdx.x == 0) {
+      gsgp_gen_stats st;
+      st.best_train_rmse = b.v;
+      st.best_test_rmse = gen_mode ? ((copied && b.i == dst) ? FtP[src] : FtO[b.i]) : FtP[b.i];
+      st.best_index = b.i;
+      st.elite_copied = copied;
+      st.elite_src = src;
+      st.elite_dst = dst;
+      R.stats[gen_mode ? gen + 1 : 0] = st;
+    }
   }
-  if (!R.state[kStReplaySelect] && gen_draw <= p.gmax) {
+  const int gen_draw = gen_mode ? gen + 2 : gen + 1;
+  if (!replay_select && gen_draw <= p.gmax) {
     const int per = (m + nb - 1) / nb;
     const int i0 = per * bl;
     const int i1 = (i0 + per) < m ? (i0 + per) : m;
     gsgp_record* out = R.rec + (int64_t)(gen_draw - 1) * m;
     for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-      out[i] = (mode == kSurvGen) ? draw_record(p, R.run_id, gen_draw, i, view_new)
-                                  : draw_record(p, R.run_id, gen_draw, i, view_cur);
+      out[i] = gen_mode ? draw_record(p, R.run_id, gen_draw, i, view_new)
+                        : draw_record(p, R.run_id, gen_draw, i, view_cur);
     }
   }
   __syncthreads();
@@ -758,7 +939,7 @@ __global__ __launch_bounds__(256) void k_survive(const RunDev* __restrict__ runs
   __syncthreads();
   if (is_last && threadIdx.x == 0) {
     R.state[kStDone] = 0;
-    if (mode == kSurvGen) {
+    if (gen_mode) {
       if (copied) {
         FO[dst] = FP[src];
         FtO[dst] = FtP[src];
@@ -928,20 +1109,28 @@ hipError_t launch_vary(const RunDev* d_runs, const Params& p, const VaryLaunch& 
 }
 
 hipError_t launch_fitness(const RunDev* d_runs, const Params& p, bool init, hipStream_t s) {
-  const int64_t total = (int64_t)p.n_runs * p.m;
-  hipLaunchKernelGGL(k_fitness, dim3(blocks_for(total, 4)), dim3(256), 0, s, d_runs, p, total,
-                     init ? 1 : 0);
+  const int32_t per_run = (p.m + kWave - 1) / kWave;
+  hipLaunchKernelGGL(k_fitness, dim3((unsigned)(per_run * p.n_runs)), dim3(kFitWaves * kWave), 0, s, d_runs, p,
+                     per_run, init ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_survive(const RunDev* d_runs, const Params& p, int32_t total_blocks, int mode,
                           hipStream_t s) {
-  if (p.precision == GSGP_FP64)
-    hipLaunchKernelGGL(k_survive<double>, dim3(total_blocks), dim3(256), 0, s, d_runs, p, total_blocks,
-                       mode);
-  else
-    hipLaunchKernelGGL(k_survive<float>, dim3(total_blocks), dim3(256), 0, s, d_runs, p, total_blocks,
-                       mode);
+  const bool lds = p.m <= kSurvLdsMaxM;
+  const size_t shmem = lds ? (size_t)2 * p.m * sizeof(double) : 0;
+  const dim3 grid(total_blocks), block(256);
+  if (p.precision == GSGP_FP64) {
+    if (lds)
+      hipLaunchKernelGGL((k_survive<double, true>), grid, block, shmem, s, d_runs, p, total_blocks, mode);
+    else
+      hipLaunchKernelGGL((k_survive<double, false>), grid, block, 0, s, d_runs, p, total_blocks, mode);
+  } else {
+    if (lds)
+      hipLaunchKernelGGL((k_survive<float, true>), grid, block, shmem, s, d_runs, p, total_blocks, mode);
+    else
+      hipLaunchKernelGGL((k_survive<float, false>), grid, block, 0, s, d_runs, p, total_blocks, mode);
+  }
   return hipGetLastError();
 }
 

@@ -117,8 +117,9 @@ gsgp_status make_plan(const gsgp_config* c, const gsgp_run* runs, int32_t n_runs
     p.tr_pad = pad_to(d.n_train, kSegPad);
     p.te_pad = pad_to(d.n_test, kSegPad);
     p.ld = p.tr_pad + p.te_pad;
-    p.nch_tr = (int32_t)((p.tr_pad + kChunk - 1) / kChunk);
-    p.nch_te = (int32_t)((p.te_pad + kChunk - 1) / kChunk);
+    const int64_t chunk = chunk_cases((int)s);
+    p.nch_tr = (int32_t)((p.tr_pad + chunk - 1) / chunk);
+    p.nch_te = (int32_t)((p.te_pad + chunk - 1) / chunk);
     auto take = [&](size_t bytes) {
       const size_t at = off;
       off = align_up(off + bytes);
@@ -164,6 +165,7 @@ struct gsgp_handle {
   int64_t interp_tasks = 0;
   int32_t surv_blocks = 0;
   int32_t depth = 1;
+  int32_t max_blocks = 0;
   int32_t gen = 0;
   bool evaluated = false;
   bool poisoned = false;
@@ -201,10 +203,11 @@ void drop_graph(gsgp_handle* h) {
 
 // Variation launch for the current shape.  With remap the grid is a multiple
 // of 8 so that logical blocks can be spread XCD by XCD.
-void plan_vary(gsgp_handle* h, int32_t waves, int32_t opb, int32_t remap) {
+void plan_vary(gsgp_handle* h, int32_t waves, int32_t opb, int32_t remap, int32_t max_blocks) {
   VaryLaunch& v = h->vary;
   v.waves = waves;
   v.opb = opb;
+  h->max_blocks = max_blocks;
   v.ogroups = (h->cfg.pop_size + opb - 1) / opb;
   v.remap = remap;
   int64_t t = 0;
@@ -213,7 +216,11 @@ void plan_vary(gsgp_handle* h, int32_t waves, int32_t opb, int32_t remap) {
     t += (int64_t)h->runs_h[i].nch * v.ogroups;
   }
   v.total_tasks = t;
-  int64_t grid = std::min<int64_t>(t, (int64_t)1 << 30);
+  // max_blocks > 0 makes the launch persistent: blocks loop over tasks
+  int64_t need = t;
+  // remap 2 walks super-groups of 8 * ogroups tasks, one group per XCD
+  if (remap == 2) need = pad_to(t, 8 * (int64_t)v.ogroups);
+  int64_t grid = std::min<int64_t>(need, max_blocks > 0 ? max_blocks : ((int64_t)1 << 30));
   if (remap) grid = pad_to(grid, 8);
   v.grid = grid;
 }
@@ -281,13 +288,24 @@ gsgp_status check_run(gsgp_handle* h, int32_t run) {
   return GSGP_OK;
 }
 
+// Unpacks a chunk-tiled semantic buffer (see chunk_geom) into FP64 rows of
+// n_train + n_test cases.
 template <typename T>
 void to_f64(const std::vector<char>& raw, int64_t rows, const RunDev& R, double* out) {
   const T* s = (const T*)raw.data();
   const int64_t n_all = R.n_train + R.n_test;
-  for (int64_t i = 0; i < rows; ++i) {
-    for (int64_t c = 0; c < R.n_train; ++c) out[i * n_all + c] = (double)s[i * R.ld + c];
-    for (int64_t c = 0; c < R.n_test; ++c) out[i * n_all + R.n_train + c] = (double)s[i * R.ld + R.tr_pad + c];
+  const int64_t CH = chunk_cases((int)sizeof(T));
+  for (int32_t c = 0; c < R.nch; ++c) {
+    const ChunkGeom g = chunk_geom(R.tr_pad, R.te_pad, R.nch_tr, c, CH);
+    const bool train = c < R.nch_tr;
+    const int64_t first = train ? g.cs : g.cs - R.tr_pad;              // case index in its segment
+    const int64_t real = (train ? R.n_train : R.n_test) - first;      // real cases left in the segment
+    const int64_t used = std::min<int64_t>(g.len, std::max<int64_t>(real, 0));
+    const int64_t out0 = train ? first : R.n_train + first;
+    for (int64_t i = 0; i < rows; ++i) {
+      const T* src = s + rows * g.cs + i * g.len;
+      for (int64_t k = 0; k < used; ++k) out[i * n_all + out0 + k] = (double)src[k];
+    }
   }
 }
 
@@ -408,13 +426,14 @@ gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_ru
     R.interp_task0 = itask;
     itask += (int64_t)rows * ((q.ld + 127) / 128);
     R.surv_blk0 = sblk;
-    int64_t nb = (q.ld + 16383) / 16384;
-    R.surv_blks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nb, 32));
+    // survival blocks per run: each copies about 16 KiB of an elite row
+    const int64_t nb = ((int64_t)storage_bytes(cfg->precision) * q.ld + 16383) / 16384;
+    R.surv_blks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nb, 64));
     sblk += R.surv_blks;
   }
   h->interp_tasks = itask;
   h->surv_blocks = sblk;
-  plan_vary(h, 4, 4, n_runs == 1 ? 1 : 0);
+  plan_vary(h, 4, 16, 1, 0);
   plan_rows(h);
 
   std::vector<const double*> src(4 * (size_t)n_runs);
@@ -703,15 +722,17 @@ gsgp_status gsgp_time_stages(gsgp_handle* h, int32_t n_gens, double* h_ms) {
   return result;
 }
 
-gsgp_status gsgp_set_launch(gsgp_handle* h, int32_t waves_per_block, int32_t offspring_per_block, int32_t xcd_remap) {
+gsgp_status gsgp_set_launch(gsgp_handle* h, int32_t waves_per_block, int32_t offspring_per_block, int32_t xcd_remap,
+                            int32_t max_blocks) {
   gsgp_status st = usable(h);
   if (st != GSGP_OK) return st;
   const int32_t w = waves_per_block ? waves_per_block : h->vary.waves;
   const int32_t o = offspring_per_block ? offspring_per_block : h->vary.opb;
   if (w < 1 || w > 8) return fail(GSGP_ERR_ARG, "waves_per_block must be in [1, 8]");
   if (o < 1 || o > 4096) return fail(GSGP_ERR_ARG, "offspring_per_block must be in [1, 4096]");
-  if (xcd_remap != 0 && xcd_remap != 1) return fail(GSGP_ERR_ARG, "xcd_remap must be 0 or 1");
-  plan_vary(h, w, o, xcd_remap);
+  if (xcd_remap < 0 || xcd_remap > 2) return fail(GSGP_ERR_ARG, "xcd_remap must be 0, 1 or 2");
+  if (max_blocks < 0) return fail(GSGP_ERR_ARG, "max_blocks must be >= 0");
+  plan_vary(h, w, o, xcd_remap, max_blocks);
   plan_rows(h);
   HIPCHK(h, upload_runs(h));
   drop_graph(h);
@@ -730,14 +751,17 @@ gsgp_status gsgp_autotune(gsgp_handle* h, int32_t* h_best) {
   HIPCHK(h, hipEventCreate(&e0));
   HIPCHK(h, hipEventCreate(&e1));
   float best_ms = 1e30f;
-  int32_t best[3] = {keep.waves, keep.opb, keep.remap};
+  int32_t best[4] = {keep.waves, keep.opb, keep.remap, h->max_blocks};
   const int32_t wave_opts[] = {2, 4, 8};
   const int32_t opb_mult[] = {1, 2, 4, 8};
+  const int32_t grid_opts[] = {0, 1024, 2048, 4096};
   gsgp_status result = GSGP_OK;
   for (int32_t w : wave_opts) {
     for (int32_t mult : opb_mult) {
-      for (int32_t remap = 0; remap <= 1 && result == GSGP_OK; ++remap) {
-        plan_vary(h, w, w * mult, remap);
+      for (int32_t trial = 0; trial < 12 && result == GSGP_OK; ++trial) {
+        const int32_t remap = trial % 3;
+        const int32_t cap = grid_opts[trial / 3];
+        plan_vary(h, w, w * mult, remap, cap);
         hipError_t x = upload_runs(h);
         for (int rep = 0; rep < 2 && x == hipSuccess; ++rep) x = launch_vary(h->runs_d, h->params, h->vary, false, h->stream);
         if (x == hipSuccess) x = hipEventRecord(e0, h->stream);
@@ -755,6 +779,7 @@ gsgp_status gsgp_autotune(gsgp_handle* h, int32_t* h_best) {
           best[0] = w;
           best[1] = w * mult;
           best[2] = remap;
+          best[3] = cap;
         }
       }
     }
@@ -762,7 +787,7 @@ gsgp_status gsgp_autotune(gsgp_handle* h, int32_t* h_best) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (result != GSGP_OK) return result;
-  plan_vary(h, best[0], best[1], best[2]);
+  plan_vary(h, best[0], best[1], best[2], best[3]);
   plan_rows(h);
   HIPCHK(h, upload_runs(h));
   drop_graph(h);

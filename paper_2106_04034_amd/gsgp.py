@@ -94,7 +94,7 @@ def lib():
             "gsgp_get_stats": [P, I32, I32, I32, P],
             "gsgp_get_genomes": [P, I32, P, P],
             "gsgp_time_stages": [P, I32, P],
-            "gsgp_set_launch": [P, I32, I32, I32],
+            "gsgp_set_launch": [P, I32, I32, I32, I32],
             "gsgp_autotune": [P, P],
             "gsgp_destroy": [P],
         }
@@ -328,10 +328,13 @@ class Runner:
         check(lib().gsgp_time_stages(self._h, n, _ptr(ms)), "gsgp_time_stages")
         return {"survive_ms": ms[0], "vary_ms": ms[1], "fitness_ms": ms[2], "generation_ms": ms[3]}
 
-    def set_launch(self, waves: int = 0, offspring_per_block: int = 0, xcd_remap: int = 1) -> None:
-        check(lib().gsgp_set_launch(self._h, waves, offspring_per_block, xcd_remap), "gsgp_set_launch")
+    def set_launch(self, waves: int = 0, offspring_per_block: int = 0, xcd_remap: int = 1,
+                   max_blocks: int = 0) -> None:
+        check(lib().gsgp_set_launch(self._h, waves, offspring_per_block, xcd_remap, max_blocks),
+              "gsgp_set_launch")
 
     def autotune(self):
-        best = np.zeros(3, np.int32)
+        best = np.zeros(4, np.int32)
         check(lib().gsgp_autotune(self._h, _ptr(best)), "gsgp_autotune")
-        return {"waves": int(best[0]), "offspring_per_block": int(best[1]), "xcd_remap": int(best[2])}
+        return {"waves": int(best[0]), "offspring_per_block": int(best[1]), "xcd_remap": int(best[2]),
+                "max_blocks": int(best[3])}

@@ -151,7 +151,7 @@ def test_launch_shapes_do_not_change_bits():
     d = dataset(3000, 700, 5, seed=4)
     s = gsgp.Settings(pop_size=50, pool_size=30, n_generations_max=4, seed=8, precision=gsgp.FP32)
     ref = None
-    for shape in [(4, 4, 1), (1, 1, 0), (8, 64, 1), (2, 6, 0)]:
+    for shape in [(4, 4, 1, 0), (1, 1, 0, 0), (8, 64, 1, 0), (2, 6, 0, 0), (4, 16, 1, 64), (4, 8, 0, 37), (4, 4, 2, 0), (2, 3, 2, 24)]:
         R = _runner(s, [d])
         R.set_launch(*shape)
         R.eval_population()
