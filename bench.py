@@ -7,11 +7,21 @@ fitness and survival.  Inputs are resident in HBM before timing starts.
 
 Default workload (single_fp32_100k): 100,000 train / 25,000 test cases,
 20 features U[-1, 1], sparse cubic target + N(0, 0.05), population 1,024,
-pool 1,024, 1,000 generations, FP32 semantics.
+pool 1,024, 1,000 generations, FP32 semantics.  It prints one JSON line:
+offspring semantic elements/s (m * n_all * G per step), the roofline of the
+dominant kernel (variation + fitness partials) from HIP events on the library
+stream, and the CPU oracle's rate on a bounded sample.
 
-Prints one JSON line: offspring semantic elements/s (m * n_all * G per step),
-the roofline of the dominant kernel (variation + fitness partials) from HIP
-events on the library stream, and the CPU oracle's rate on a bounded sample.
+Other workloads (--workload) print their own line:
+  large_fp32_1m    the same measurement on 1,000,000 / 250,000 cases, m = 2,048;
+  plain_fp64_500x8 the same measurement on the small FP64 workload;
+  precision_1m     FP32 and FP32-Kahan runs against an FP64 replay of the same
+                   lineage: relative fitness drift per generation;
+  batched_256      256 uneven runs in one handle (FP32-Kahan, graph) against
+                   the plain per-run forms: runs/hour and fitness error;
+  paper_shape_k127 / _k1023 / _k2047
+                   the shape of the paper's speed-up study (Section 3.1): stage
+                   times in its categories next to the single-thread oracle.
 """
 from __future__ import annotations
 
@@ -102,45 +112,22 @@ def cpu_baseline(workload, data, G: int, seed: int, frac: int = 4, g_sample: int
             "sample": sample, "gen_elements_per_s": workload.pop_size * (ntr + nte) * g_sample / (t2 - t1)}
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="single_fp32_100k")
-    ap.add_argument("--stage-gens", type=int, default=50)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--generations", type=int, default=0,
-                    help="override the workload's generation count (profiling runs only)")
-    ap.add_argument("--launch", default="",
-                    help="variation launch shape waves,offspring_per_block,xcd_remap,max_blocks "
-                         "(skips autotuning)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              "(a single run shards over fitness cases only in design, see the design notes)",
-              file=sys.stderr)
-        return 2
+def settings_for(gsgp, wl, G, precision, seed, flags=0):
+    return gsgp.Settings(pop_size=wl.pop_size, pool_size=wl.pool_size, genome_len=wl.genome_len,
+                         n_generations_max=G, tournament_size=wl.tournament_size,
+                         p_crossover=wl.p_crossover, mutation_step=wl.mutation_step,
+                         precision=precision, seed=seed, flags=flags)
 
+
+def bench_single(args, wl, data, seed) -> dict:
+    """Whole runs of one workload; elements/s, roofline and CPU baseline."""
     import torch
-    from paper_2106_04034_amd import gsgp, synth
+    from paper_2106_04034_amd import gsgp
 
-    wl = synth.WORKLOADS[args.workload]
-    if wl.name != "single_fp32_100k":
-        print(f"bench.py: workload {wl.name} has no bench line; use the default", file=sys.stderr)
-        return 2
-    data = synth.single_run(wl.n_train, wl.n_test, wl.n_features)
     G = args.generations or wl.generations
-    seed = synth.evolution_seed(1)
     prec = gsgp.PRECISIONS[wl.precision]
-    settings = gsgp.Settings(pop_size=wl.pop_size, pool_size=wl.pool_size, genome_len=wl.genome_len,
-                             n_generations_max=G, tournament_size=wl.tournament_size,
-                             p_crossover=wl.p_crossover, mutation_step=wl.mutation_step,
-                             precision=prec, seed=seed)
-    stream = torch.cuda.Stream()
-    R = gsgp.Runner(settings, [data], stream=stream)
-    n_all = wl.n_train + wl.n_test
+    R = gsgp.Runner(settings_for(gsgp, wl, G, prec, seed), [data], stream=torch.cuda.Stream())
+    n_all = data.X_train.shape[0] + data.X_test.shape[0]
     m = wl.pop_size
     s_bytes = 8 if prec == gsgp.FP64 else 4
 
@@ -180,12 +167,14 @@ def main() -> int:
     stages = R.time_stages(ng)
     rec = R.records(0, 1, ng)
     chunk = 4096 // s_bytes  # canonical chunk: 4 KiB of a semantic row
-    n_chunks = -(-(-(-wl.n_train // 64) * 64) // chunk) + -(-(-(-wl.n_test // 64) * 64) // chunk)
+    n_tr, n_te = data.X_train.shape[0], data.X_test.shape[0]
+    n_chunks = -(-(-(-n_tr // 64) * 64) // chunk) + -(-(-(-n_te // 64) * 64) // chunk)
     per_launch = float(np.mean([vary_bytes(rec[g], n_all, s_bytes, m, n_chunks) for g in range(ng)]))
     u = np.array([distinct_rows(rec[g]) for g in range(ng)])
     achieved = per_launch / (stages["vary_ms"] * 1e-3) / 1e9
-    traffic = traffic_from_profile(per_launch)
+    traffic = traffic_from_profile(per_launch) if wl.name == "single_fp32_100k" else None
     gen_rate = m * n_all / (stages["generation_ms"] * 1e-3)
+    R.close()
 
     out = {
         "metric": "offspring semantic elements/s (whole GSGP run incl. initialisation)",
@@ -198,10 +187,10 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if prec == gsgp.FP64 else "f32",
         "data": "synthetic",
-        "config": {"workload": wl.name, "n_train": wl.n_train, "n_test": wl.n_test,
-                   "n_features": wl.n_features, "pop_size": m, "pool_size": wl.pool_size,
+        "config": {"workload": wl.name, "n_train": n_tr, "n_test": n_te,
+                   "n_features": data.X_train.shape[1], "pop_size": m, "pool_size": wl.pool_size,
                    "genome_len": wl.genome_len, "generations": G, "tournament_size": wl.tournament_size,
                    "p_crossover": wl.p_crossover, "mutation_step": wl.mutation_step,
                    "precision": wl.precision, "launch": tuned},
@@ -217,11 +206,254 @@ def main() -> int:
         "final_best_train_rmse": float(final["best_train_rmse"]),
         "final_best_test_rmse": float(final["best_test_rmse"]),
     }
-    R.close()
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(wl, data, G, seed)
+        frac = 4 if n_all <= 200_000 else 32
+        if n_all < 10_000:
+            frac = 1
+        cb = cpu_baseline(wl, data, G, seed, frac=frac)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         out["cpu_baseline"]["gen_elements_per_s"] = cb["gen_elements_per_s"]
+    return out
+
+
+def bench_precision(args) -> dict:
+    """FP32 and FP32-Kahan runs, each followed by an FP64 replay of the same
+    lineage (records and survival decisions) on the GPU; relative fitness
+    drift per generation for the best individual and over the population.
+    The GPU FP64 form is parity-checked against the CPU oracle in the tests."""
+    import torch
+    from paper_2106_04034_amd import gsgp, synth
+
+    wl = synth.WORKLOADS["precision_1m"]
+    G = args.generations or wl.generations
+    data = synth.large_run()
+    seed = synth.evolution_seed(3)
+    m = wl.pop_size
+    report = {}
+    for name, prec in (("fp32", gsgp.FP32), ("fp32_kahan", gsgp.FP32_KAHAN)):
+        R = gsgp.Runner(settings_for(gsgp, wl, G, prec, seed), [data], stream=torch.cuda.Stream())
+        R.eval_population()
+        F32 = [R.fitness(0)[0]]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(G):
+            R.generation(1, stats=False)
+            F32.append(R.fitness(0)[0])
+        t32 = time.perf_counter() - t0
+        rec = R.records(0, 1, G)
+        elite = R.stats(0, 1, G)
+        best = R.stats(0, 0, G + 1)["best_index"]
+        R.close()
+        R64 = gsgp.Runner(settings_for(gsgp, wl, G, gsgp.FP64, seed), [data], stream=torch.cuda.Stream())
+        R64.eval_population()
+        F64 = [R64.fitness(0)[0]]
+        for g in range(G):
+            R64.replay(rec[g:g + 1], elite[g:g + 1], stats=False)
+            F64.append(R64.fitness(0)[0])
+        R64.close()
+        F32, F64 = np.array(F32), np.array(F64)
+        drift = np.abs(F32 - F64) / F64
+        best_drift = drift[np.arange(G + 1), best]
+        report[name] = {
+            "best_drift_max": float(best_drift.max()),
+            "best_drift_final": float(best_drift[-1]),
+            "median_drift_max": float(np.median(drift, axis=1).max()),
+            "population_drift_max": float(drift.max()),
+            "final_best_rmse_fp32": float(F32[-1][best[-1]]),
+            "final_best_rmse_fp64_replay": float(F64[-1][best[-1]]),
+            "best_drift_every_100": [float(best_drift[g]) for g in range(0, G + 1, 100)],
+            "generation_loop_s_with_readback": t32,
+        }
+    ok = all(v["best_drift_final"] <= 1e-4 for v in report.values())
+    return {"metric": "relative fitness drift vs FP64 replay of the same lineage",
+            "value": report["fp32_kahan"]["best_drift_final"], "unit": "relative",
+            "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+            "config": {"workload": wl.name, "n_train": data.X_train.shape[0],
+                       "n_test": data.X_test.shape[0], "n_features": data.X_train.shape[1],
+                       "pop_size": m, "pool_size": wl.pool_size, "generations": G},
+            "forms": report, "end_of_run_within_1e-4": ok}
+
+
+def bench_batched(args) -> dict:
+    """256 uneven runs: one batched FP32-Kahan handle (HIP graph) against the
+    plain per-run form (one FP64 handle per run, launches one by one) and a
+    per-run FP32-Kahan form; whole runs timed, set-up excluded.  Fitness error
+    of the batched runs against an FP64 replay of their own lineages."""
+    import torch
+    from paper_2106_04034_amd import gsgp, synth
+
+    wl = synth.WORKLOADS["batched_256"]
+    G = args.generations or wl.generations
+    n_runs = args.runs or wl.runs
+    datasets = synth.batched_runs(n_runs)
+    seed = synth.evolution_seed(4)
+    stream = torch.cuda.Stream()
+    out = {}
+
+    B = gsgp.Runner(settings_for(gsgp, wl, G, gsgp.FP32_KAHAN, seed), datasets, stream=stream)
+    B.eval_population()
+    B.generation(min(G, 3), stats=False)  # warm up graph capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.eval_population()
+    B.generation(G, stats=False)
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    rec = np.stack([B.records(j, 1, G) for j in range(n_runs)])
+    elite = np.stack([B.stats(j, 1, G) for j in range(n_runs)])
+    final = np.stack([B.stats(j, G, 1)[0] for j in range(n_runs)])
+    F_b = np.stack([B.fitness(j)[0] for j in range(n_runs)])
+    B.close()
+
+    R64 = gsgp.Runner(settings_for(gsgp, wl, G, gsgp.FP64, seed), datasets, stream=stream)
+    R64.eval_population()
+    R64.replay(rec, elite, stats=False)
+    F_64 = np.stack([R64.fitness(j)[0] for j in range(n_runs)])
+    R64.close()
+    idx = final["best_index"]
+    err = np.abs(F_b[np.arange(n_runs), idx] - F_64[np.arange(n_runs), idx]) / F_64[np.arange(n_runs), idx]
+
+    def per_run(precision, flags):
+        total = 0.0
+        for j, d in enumerate(datasets):
+            R = gsgp.Runner(settings_for(gsgp, wl, G, precision, seed + j, flags), [d], stream=stream)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            R.eval_population()
+            R.generation(G, stats=False)
+            torch.cuda.synchronize()
+            total += time.perf_counter() - t
+            R.close()
+        return total
+
+    t_plain = per_run(gsgp.FP64, gsgp.FLAG_NO_GRAPH)
+    t_single32 = per_run(gsgp.FP32_KAHAN, 0)
+    n_all = sum(d.X_train.shape[0] + d.X_test.shape[0] for d in datasets)
+    return {"metric": "runs/hour, batched FP32-Kahan vs plain per-run", "value": n_runs * 3600 / t_batched,
+            "unit": "runs/hour", "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
+            "config": {"workload": wl.name, "runs": n_runs, "total_cases": n_all, "pop_size": wl.pop_size,
+                       "pool_size": wl.pool_size, "generations": G},
+            "batched_fp32_kahan_graph": {"runs_per_hour": n_runs * 3600 / t_batched, "seconds": t_batched,
+                                         "offspring_elements_per_s": wl.pop_size * n_all * G / t_batched},
+            "plain_per_run_fp64": {"runs_per_hour": n_runs * 3600 / t_plain, "seconds": t_plain},
+            "per_run_fp32_kahan_graph": {"runs_per_hour": n_runs * 3600 / t_single32, "seconds": t_single32},
+            "speedup_vs_plain": t_plain / t_batched,
+            "best_fitness_rel_err_vs_fp64_replay": {"max": float(err.max()), "median": float(np.median(err))},
+            "within_1e-4": bool(err.max() <= 1e-4)}
+
+
+def bench_paper_shape(args, wl) -> dict:
+    """The speed-up study's shape (Section 3.1): CreatePopulation,
+    ComputeSemantics, one generation and total run time on the GPU, each next
+    to the single-thread FP64 oracle timed on a slice (all programs, 1/64 of
+    the cases at k = 127, fewer for longer programs; genome generation in
+    full) and scaled linearly in cases."""
+    import torch
+    from oracle import oracle as orc
+    from paper_2106_04034_amd import gsgp, synth
+
+    G = args.generations or wl.generations
+    data = synth.paper_shape(wl.n_train, wl.n_features)
+    seed = synth.evolution_seed(5)
+    s = settings_for(gsgp, wl, G, gsgp.FP32, seed)
+    s.ms_random = 1
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    # Total run time as the paper takes it: host data in, whole run, the
+    # final fitness back on the host.
+    t0 = time.perf_counter()
+    R = gsgp.Runner(s, [data], stream=stream)
+    R.eval_population()
+    R.generation(G, stats=False)
+    F_final, _ = R.fitness(0)
+    total_s = time.perf_counter() - t0
+    ev = R.time_eval()
+    stages = R.time_stages(min(G, 20))
+    R.close()
+
+    orc.set_threads(1)
+    cfg = orc.Config(pop_size=wl.pop_size, pool_size=wl.pool_size, genome_len=wl.genome_len,
+                     tournament_size=0, p_crossover=0.0, ms_random=1, seed=seed)
+    t = time.perf_counter()
+    cp, vp = orc.genomes(cfg, wl.n_features, orc.TAG_POPULATION, wl.pop_size)
+    cr, vr = orc.genomes(cfg, wl.n_features, orc.TAG_POOL, wl.pool_size)
+    c_create = time.perf_counter() - t
+    frac = 64 * max(1, (wl.genome_len + 1) // 128)       # ~15 s of oracle work at every size
+    ncs = wl.n_train // frac
+    Xs, ys = data.X_train[:ncs], data.y_train[:ncs]
+    t = time.perf_counter()
+    S = orc.interpret(cp, vp, Xs)
+    sig = orc.sigmoid(orc.interpret(cr, vr, Xs))
+    c_sem = (time.perf_counter() - t) * frac
+    F = orc.rmse_rows(S, ys)
+    t = time.perf_counter()
+    gens = 3
+    for g in range(1, gens + 1):
+        rec = orc.select(cfg, g, F)
+        O = orc.vary(rec, S, sig)
+        F_O = orc.rmse_rows(O, ys)
+        no_test = np.zeros((wl.pop_size, 0))
+        orc.survive(F, F.copy(), F_O, F_O.copy(), S, O, no_test, no_test.copy())
+        S, F = O, F_O
+    c_gen = (time.perf_counter() - t) / gens * frac
+    orc.set_threads(len(os.sched_getaffinity(0)))
+    c_total = c_create + c_sem + G * c_gen                  # resident data: no load time
+    gpu = {"create_population_ms": ev["create_population_ms"], "compute_semantics_ms": ev["compute_semantics_ms"],
+           "generation_ms": stages["generation_ms"], "total_run_ms": total_s * 1e3}
+    cpu = {"create_population_ms": c_create * 1e3, "compute_semantics_ms": c_sem * 1e3,
+           "generation_ms": c_gen * 1e3, "total_run_ms": c_total * 1e3}
+    return {"metric": "stage speed-up over the single-thread FP64 oracle (paper's categories)",
+            "value": cpu["generation_ms"] / gpu["generation_ms"], "unit": "x (one generation)",
+            "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
+            "config": {"workload": wl.name, "n_train": wl.n_train, "n_features": wl.n_features,
+                       "pop_size": wl.pop_size, "pool_size": wl.pool_size, "genome_len": wl.genome_len,
+                       "generations": G, "loop": "mutate every individual, random step", "precision": "fp32"},
+            "gpu": gpu, "cpu_oracle_1_thread": cpu, "best_train_rmse": float(np.min(F_final)),
+            "speedup": {k: cpu[k] / gpu[k] for k in gpu},
+            "cpu_sample": f"genomes in full; semantics and {gens} generations on 1/{frac} of the cases, "
+                          "scaled linearly in cases"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="single_fp32_100k")
+    ap.add_argument("--stage-gens", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--generations", type=int, default=0,
+                    help="override the workload's generation count (profiling runs only)")
+    ap.add_argument("--runs", type=int, default=0, help="batched_256: number of runs (default 256)")
+    ap.add_argument("--launch", default="",
+                    help="variation launch shape waves,offspring_per_block,xcd_remap,max_blocks "
+                         "(skips autotuning)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(a single run shards over fitness cases only in design, see the design notes)",
+              file=sys.stderr)
+        return 2
+
+    from paper_2106_04034_amd import synth
+
+    wl = synth.WORKLOADS[args.workload]
+    if wl.name == "single_fp32_100k":
+        out = bench_single(args, wl, synth.single_run(wl.n_train, wl.n_test, wl.n_features),
+                           synth.evolution_seed(1))
+    elif wl.name == "large_fp32_1m":
+        out = bench_single(args, wl, synth.large_run(wl.n_train, wl.n_test, wl.n_features),
+                           synth.evolution_seed(2))
+    elif wl.name == "plain_fp64_500x8":
+        out = bench_single(args, wl, synth.plain_small(wl.n_train, wl.n_test, wl.n_features),
+                           synth.evolution_seed(0))
+    elif wl.name == "precision_1m":
+        out = bench_precision(args)
+    elif wl.name.startswith("paper_shape"):
+        out = bench_paper_shape(args, wl)
+    else:
+        out = bench_batched(args)
     print(json.dumps(out))
     return 0
 

@@ -229,6 +229,15 @@ gsgp_status gsgp_get_genomes(gsgp_handle* h, int32_t run, int32_t* h_codes, doub
  * fitness combination, and the whole generation.  Advances the runs. */
 gsgp_status gsgp_time_stages(gsgp_handle* h, int32_t n_gens, double* h_ms);
 
+/* Runs gsgp_eval_population (Philox genomes) with HIP events between its
+ * stages and writes the milliseconds of each to h_ms[0..3]: CreatePopulation
+ * (genomes), ComputeSemantics (genome compilation and interpretation of
+ * population and pool, including one small read-back), initial fitness and
+ * the first variation draws, and the whole initialisation -- the stage
+ * categories of the paper's speed-up study (Section 3.1).  Restarts the runs
+ * at generation 0.  Errors: as gsgp_eval_population. */
+gsgp_status gsgp_time_eval(gsgp_handle* h, double* h_ms);
+
 /* Launch shape of the variation kernel: waves per block (1..8) and
  * offspring per block task (0 keeps the current value for either), XCD-aware
  * block order (0 none; 1 each XCD takes a contiguous range of tasks; 2 the

@@ -69,7 +69,7 @@ struct RunDev {
   int32_t surv_blk0, surv_blks; // survival kernel blocks of this run
   int32_t pad0;
   int64_t vary_task0;       // first task of this run in the variation launch
-  int64_t interp_task0;     // first task of this run in the interpreter launch
+  int64_t cblk0;            // first 128-case block of this run (interpreter)
   int64_t col0;             // first padded column of this run (data prep)
 };
 
@@ -141,8 +141,8 @@ hipError_t launch_set_state(const RunDev* d_runs, int32_t n_runs, int32_t word, 
                             hipStream_t s);
 hipError_t launch_genome(const RunDev* d_runs, const Params& p, hipStream_t s);
 hipError_t launch_compile(const RunDev* d_runs, const Params& p, hipStream_t s);
-hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t total_tasks, int depth,
-                            hipStream_t s);
+hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_blocks, int max_features,
+                            int depth, hipStream_t s);
 hipError_t launch_vary(const RunDev* d_runs, const Params& p, const VaryLaunch& lc, bool rows_only,
                        hipStream_t s);
 hipError_t launch_fitness(const RunDev* d_runs, const Params& p, bool init, hipStream_t s);

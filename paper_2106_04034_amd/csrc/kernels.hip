@@ -285,50 +285,71 @@ __device__ __forceinline__ void eval_program(const int32_t* __restrict__ ops,
   for (int v = 0; v < V; ++v) out[v] = tos[v];
 }
 
-constexpr int kInterpV = 2;  // cases per lane
+constexpr int kInterpV = 2;              // cases per lane
+constexpr int kInterpTile = kWave * kInterpV;  // cases per block
+constexpr int kInterpProgsPerWave = 4;   // programs each wave interprets on its case block
 
-// ComputeSemantics(P) and ComputeSemantics(R) (Algorithm 1): one wavefront
-// per (program, block of 128 cases).  Pool rows are squashed by the logistic
-// function (the random functions R_u of GSM, Section 2) before storage.
-// Padding columns are written as exact zeros.
-template <typename T>
-__global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ runs, Params p,
-                                                   int64_t total, int depth) {
+// ComputeSemantics(P) and ComputeSemantics(R) (Algorithm 1).  A block takes
+// one block of 128 cases of one run and a group of programs; with XLDS the
+// block first stages the cases' features in LDS so feature pushes read LDS,
+// then each wave interprets kInterpProgsPerWave programs.  Pool rows are
+// squashed by the logistic function (the random functions R_u of GSM,
+// Section 2) before storage.  Padding columns are written as exact zeros.
+template <typename T, bool XLDS>
+__global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ runs, Params p, int32_t pgroups,
+                                                   int depth, int32_t xtile_doubles) {
   extern __shared__ double lds[];
   const int lane = threadIdx.x & 63;
   const int wave = uni(threadIdx.x >> 6);
-  const int64_t task = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
-  if (task >= total) return;
-  const int run = find_run(p.n_runs, task, [&](int r) { return runs[r].interp_task0; });
+  const int W = blockDim.x >> 6;
+  const int64_t cbg = blockIdx.x / pgroups;  // case block over all runs
+  const int pg = (int)(blockIdx.x - cbg * pgroups);
+  const int run = find_run(p.n_runs, cbg, [&](int r) { return runs[r].cblk0; });
   const RunDev& R = runs[run];
-  const int64_t local = task - R.interp_task0;
-  const int rows = p.m + p.r;
-  const int64_t cb = local / rows;
-  const int prog = (int)(local - cb * rows);
+  const int64_t cb = cbg - R.cblk0;
   const int64_t ld = R.ld;
-  int64_t col[kInterpV];
+  const int rows = p.m + p.r;
+  double* stk = lds + xtile_doubles + (int64_t)wave * depth * kInterpV * kWave;
+  if constexpr (XLDS) {
+    for (int idx = threadIdx.x; idx < R.l * kInterpTile; idx += blockDim.x) {
+      const int f = idx / kInterpTile;
+      const int64_t gc = cb * kInterpTile + (idx - f * kInterpTile);
+      lds[idx] = gc < ld ? R.X[(int64_t)f * ld + gc] : 0.0;
+    }
+    __syncthreads();
+  }
+  int64_t col[kInterpV], xcol[kInterpV];
   bool ok[kInterpV];
 #pragma unroll
   for (int v = 0; v < kInterpV; ++v) {
-    col[v] = cb * (kWave * kInterpV) + v * kWave + lane;
+    col[v] = cb * kInterpTile + v * kWave + lane;
     ok[v] = col[v] < ld;
+    xcol[v] = XLDS ? (int64_t)(v * kWave + lane) : col[v];
   }
-  double out[kInterpV];
-  double* stk = lds + (int64_t)wave * depth * kInterpV * kWave;
-  eval_program<kInterpV>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k,
-                         uni(R.nops[prog]), R.X, ld, col, ok, stk, lane, out);
-  const bool pool = prog >= p.m;
-  T* dst = pool ? (T*)R.sigR : (T*)R.S[0];
-  const int64_t nrows = pool ? p.r : p.m;
-  const int64_t row = pool ? prog - p.m : prog;
+  for (int j = 0; j < kInterpProgsPerWave; ++j) {
+    const int prog = (pg * kInterpProgsPerWave + j) * W + wave;
+    if (prog >= rows) break;
+    double out[kInterpV];
+    if constexpr (XLDS)
+      eval_program<kInterpV>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k, uni(R.nops[prog]), lds,
+                             kInterpTile, xcol, ok, stk, lane, out);
+    else
+      eval_program<kInterpV>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k, uni(R.nops[prog]), R.X,
+                             ld, xcol, ok, stk, lane, out);
+    const bool pool = prog >= p.m;
+    T* dst = pool ? (T*)R.sigR : (T*)R.S[0];
+    const int64_t nrows = pool ? p.r : p.m;
+    const int64_t row = pool ? prog - p.m : prog;
 #pragma unroll
-  for (int v = 0; v < kInterpV; ++v) {
-    if (!ok[v]) continue;
-    const int64_t c = col[v];
-    const bool real = c < R.n_train || (c >= R.tr_pad && c < R.tr_pad + R.n_test);
-    double val = out[v];
-    if (pool) val = 1.0 / (1.0 + exp(-val));
-    dst[tiled_index(R.tr_pad, R.te_pad, R.nch_tr, chunk_cases(sizeof(T)), nrows, row, c)] = real ? (T)val : (T)0;
+    for (int v = 0; v < kInterpV; ++v) {
+      if (!ok[v]) continue;
+      const int64_t c = col[v];
+      const bool real = c < R.n_train || (c >= R.tr_pad && c < R.tr_pad + R.n_test);
+      double val = out[v];
+      if (pool) val = 1.0 / (1.0 + exp(-val));
+      dst[tiled_index(R.tr_pad, R.te_pad, R.nch_tr, chunk_cases(sizeof(T)), nrows, row, c)] =
+          real ? (T)val : (T)0;
+    }
   }
 }
 
@@ -984,7 +1005,7 @@ __global__ __launch_bounds__(256) void k_interpret_list(const int32_t* __restric
   double val[kInterpV];
   double* stk = lds + (int64_t)wave * depth * kInterpV * kWave;
   eval_program<kInterpV>(ops + (int64_t)pr * k, opv + (int64_t)pr * k, uni(nops[pr]), Xfm, ld, col, ok,
-                         stk, lane, val);
+                         stk, lane, val);  // column index doubles as the X offset here
   const bool sq = squash[j] != 0;
 #pragma unroll
   for (int v = 0; v < kInterpV; ++v) {
@@ -1066,18 +1087,36 @@ hipError_t launch_compile(const RunDev* d_runs, const Params& p, hipStream_t s) 
   return hipGetLastError();
 }
 
-hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t total_tasks, int depth,
-                            hipStream_t s) {
+hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_blocks, int max_features,
+                            int depth, hipStream_t s) {
   if (depth < 1) depth = 1;
-  const int waves = interp_waves(depth);
-  const size_t shmem = (size_t)waves * depth * kInterpV * kWave * sizeof(double);
-  const dim3 grid(blocks_for(total_tasks, waves));
-  if (p.precision == GSGP_FP64)
-    hipLaunchKernelGGL(k_interpret<double>, grid, dim3(waves * kWave), shmem, s, d_runs, p,
-                       total_tasks, depth);
-  else
-    hipLaunchKernelGGL(k_interpret<float>, grid, dim3(waves * kWave), shmem, s, d_runs, p,
-                       total_tasks, depth);
+  // LDS budget 64 KiB: the features of 128 cases (when staged) plus one
+  // stack column block per wave.
+  const int64_t stack_per_wave = (int64_t)depth * kInterpV * kWave * sizeof(double);
+  const int64_t xtile = (int64_t)max_features * kInterpTile * sizeof(double);
+  int waves = 4;
+  bool xlds = true;
+  while (waves > 1 && xtile + waves * stack_per_wave > 65536) --waves;
+  if (xtile + waves * stack_per_wave > 65536) {
+    xlds = false;
+    waves = interp_waves(depth);
+  }
+  const int rows = p.m + p.r;
+  const int32_t pgroups = (rows + waves * kInterpProgsPerWave - 1) / (waves * kInterpProgsPerWave);
+  const int32_t xdoubles = xlds ? (int32_t)(xtile / sizeof(double)) : 0;
+  const size_t shmem = (size_t)xdoubles * sizeof(double) + (size_t)waves * stack_per_wave;
+  const dim3 grid((unsigned)(case_blocks * pgroups)), block(waves * kWave);
+  if (p.precision == GSGP_FP64) {
+    if (xlds)
+      hipLaunchKernelGGL((k_interpret<double, true>), grid, block, shmem, s, d_runs, p, pgroups, depth, xdoubles);
+    else
+      hipLaunchKernelGGL((k_interpret<double, false>), grid, block, shmem, s, d_runs, p, pgroups, depth, xdoubles);
+  } else {
+    if (xlds)
+      hipLaunchKernelGGL((k_interpret<float, true>), grid, block, shmem, s, d_runs, p, pgroups, depth, xdoubles);
+    else
+      hipLaunchKernelGGL((k_interpret<float, false>), grid, block, shmem, s, d_runs, p, pgroups, depth, xdoubles);
+  }
   return hipGetLastError();
 }
 

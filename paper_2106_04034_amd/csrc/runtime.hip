@@ -162,7 +162,8 @@ struct gsgp_handle {
   RunDev* runs_d = nullptr;
   Params params;
   VaryLaunch vary{}, rows{};
-  int64_t interp_tasks = 0;
+  int64_t interp_tasks = 0;  // 128-case blocks over all runs
+  int32_t max_features = 0;
   int32_t surv_blocks = 0;
   int32_t depth = 1;
   int32_t max_blocks = 0;
@@ -387,7 +388,6 @@ gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_ru
   h->runs_h.resize(n_runs);
   int64_t col = 0, itask = 0;
   int32_t sblk = 0;
-  const int rows = cfg->pop_size + cfg->pool_size;
   for (int32_t i = 0; i < n_runs; ++i) {
     const RunPlan& q = plan.runs[i];
     RunDev& R = h->runs_h[i];
@@ -423,8 +423,9 @@ gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_ru
     R.run_id = (uint32_t)i;
     R.col0 = col;
     col += q.ld;
-    R.interp_task0 = itask;
-    itask += (int64_t)rows * ((q.ld + 127) / 128);
+    R.cblk0 = itask;
+    itask += (q.ld + 127) / 128;
+    h->max_features = std::max(h->max_features, q.l);
     R.surv_blk0 = sblk;
     // survival blocks per run: each copies about 16 KiB of an elite row
     const int64_t nb = ((int64_t)storage_bytes(cfg->precision) * q.ld + 16383) / 16384;
@@ -478,7 +479,12 @@ gsgp_status gsgp_destroy(gsgp_handle* h) {
   return GSGP_OK;
 }
 
-gsgp_status gsgp_eval_population(gsgp_handle* h, const int32_t* h_codes, const double* h_consts) {
+namespace {
+
+// Algorithm 1 before the loop.  ev (nullable) receives four events: start,
+// after the genomes, after the semantics (compile + interpret), and after
+// the initial fitness and first draws.
+gsgp_status eval_impl(gsgp_handle* h, const int32_t* h_codes, const double* h_consts, hipEvent_t* ev) {
   gsgp_status st = usable(h);
   if (st != GSGP_OK) return st;
   if ((h_codes == nullptr) != (h_consts == nullptr)) return fail(GSGP_ERR_ARG, "give both codes and constants, or neither");
@@ -494,6 +500,7 @@ gsgp_status gsgp_eval_population(gsgp_handle* h, const int32_t* h_codes, const d
       }
     }
   }
+  if (ev) HIPCHK(h, hipEventRecord(ev[0], h->stream));
   for (int32_t w : {kStGen, kStDone, kStReplaySelect, kStReplayElite, kStMaxDepth})
     HIPCHK(h, launch_set_state(h->runs_d, h->n_runs, w, 0, h->stream));
   if (h_codes) {
@@ -504,9 +511,8 @@ gsgp_status gsgp_eval_population(gsgp_handle* h, const int32_t* h_codes, const d
   } else {
     HIPCHK(h, launch_genome(h->runs_d, p, h->stream));
   }
+  if (ev) HIPCHK(h, hipEventRecord(ev[1], h->stream));
   HIPCHK(h, launch_compile(h->runs_d, p, h->stream));
-  const RunPlan& q0 = h->plan.runs[0];
-  (void)q0;
   int32_t* state = (int32_t*)(h->ws + h->plan.state);
   HIPCHK(h, hipMemcpyAsync(h->pinned, state, sizeof(int32_t) * kStWords * h->n_runs, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -517,13 +523,55 @@ gsgp_status gsgp_eval_population(gsgp_handle* h, const int32_t* h_codes, const d
     return fail(GSGP_ERR_UNSUPPORTED, "a genome needs a stack of %d values; at most %d are supported", deepest, kMaxStack);
   }
   h->depth = std::max(1, deepest - 1);
-  HIPCHK(h, launch_interpret(h->runs_d, p, h->interp_tasks, h->depth, h->stream));
+  HIPCHK(h, launch_interpret(h->runs_d, p, h->interp_tasks, h->max_features, h->depth, h->stream));
+  if (ev) HIPCHK(h, hipEventRecord(ev[2], h->stream));
   HIPCHK(h, launch_vary(h->runs_d, p, h->rows, true, h->stream));
   HIPCHK(h, launch_fitness(h->runs_d, p, true, h->stream));
   HIPCHK(h, launch_survive(h->runs_d, p, h->surv_blocks, kSurvInit, h->stream));
+  if (ev) HIPCHK(h, hipEventRecord(ev[3], h->stream));
   h->gen = 0;
   h->evaluated = true;
   return GSGP_OK;
+}
+
+}  // namespace
+
+gsgp_status gsgp_eval_population(gsgp_handle* h, const int32_t* h_codes, const double* h_consts) {
+  return eval_impl(h, h_codes, h_consts, nullptr);
+}
+
+gsgp_status gsgp_time_eval(gsgp_handle* h, double* h_ms) {
+  gsgp_status st = usable(h);
+  if (st != GSGP_OK) return st;
+  if (!h_ms) return fail(GSGP_ERR_ARG, "h_ms is NULL");
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  for (auto& e : ev) {
+    hipError_t x = hipEventCreate(&e);
+    if (x != hipSuccess) {
+      for (auto& f : ev)
+        if (f) (void)hipEventDestroy(f);
+      return hip_fail(h, x, "hipEventCreate");
+    }
+  }
+  st = eval_impl(h, nullptr, nullptr, ev);
+  if (st == GSGP_OK) {
+    hipError_t x = hipEventSynchronize(ev[3]);
+    float a = 0, b = 0, c = 0, d = 0;
+    if (x == hipSuccess) x = hipEventElapsedTime(&a, ev[0], ev[1]);
+    if (x == hipSuccess) x = hipEventElapsedTime(&b, ev[1], ev[2]);
+    if (x == hipSuccess) x = hipEventElapsedTime(&c, ev[2], ev[3]);
+    if (x == hipSuccess) x = hipEventElapsedTime(&d, ev[0], ev[3]);
+    if (x != hipSuccess) {
+      st = hip_fail(h, x, "timing the initialisation");
+    } else {
+      h_ms[0] = a;
+      h_ms[1] = b;
+      h_ms[2] = c;
+      h_ms[3] = d;
+    }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  return st;
 }
 
 gsgp_status gsgp_generation(gsgp_handle* h, int32_t n_gens, gsgp_gen_stats* h_stats) {

@@ -34,7 +34,7 @@ EXPORTS = [
     "gsgp_workspace_size", "gsgp_init", "gsgp_eval_population", "gsgp_generation",
     "gsgp_generation_replay", "gsgp_reconstruct_scratch_size", "gsgp_reconstruct",
     "gsgp_current_generation", "gsgp_get_fitness", "gsgp_get_semantics", "gsgp_get_records",
-    "gsgp_get_stats", "gsgp_get_genomes", "gsgp_time_stages", "gsgp_set_launch",
+    "gsgp_get_stats", "gsgp_get_genomes", "gsgp_time_stages", "gsgp_time_eval", "gsgp_set_launch",
     "gsgp_autotune", "gsgp_destroy", "gsgp_status_string", "gsgp_last_error",
 ]
 
@@ -94,6 +94,7 @@ def lib():
             "gsgp_get_stats": [P, I32, I32, I32, P],
             "gsgp_get_genomes": [P, I32, P, P],
             "gsgp_time_stages": [P, I32, P],
+            "gsgp_time_eval": [P, P],
             "gsgp_set_launch": [P, I32, I32, I32, I32],
             "gsgp_autotune": [P, P],
             "gsgp_destroy": [P],
@@ -327,6 +328,13 @@ class Runner:
         ms = np.zeros(4)
         check(lib().gsgp_time_stages(self._h, n, _ptr(ms)), "gsgp_time_stages")
         return {"survive_ms": ms[0], "vary_ms": ms[1], "fitness_ms": ms[2], "generation_ms": ms[3]}
+
+    def time_eval(self) -> dict:
+        """Initialisation with per-stage HIP-event timing (restarts the runs)."""
+        ms = np.zeros(4)
+        check(lib().gsgp_time_eval(self._h, _ptr(ms)), "gsgp_time_eval")
+        return {"create_population_ms": ms[0], "compute_semantics_ms": ms[1],
+                "initial_fitness_ms": ms[2], "eval_total_ms": ms[3]}
 
     def set_launch(self, waves: int = 0, offspring_per_block: int = 0, xcd_remap: int = 1,
                    max_blocks: int = 0) -> None:

@@ -62,6 +62,15 @@ WORKLOADS = {
     "batched_256": Workload("batched_256", 0, 0, 0, 256, 256, 300, "fp32_kahan", runs=256,
                             notes="n per run log-uniform in [200, 50000], test n/4, 4..32 features"),
 }
+# The speed-up study's shape (Section 3.1): 102,400 cases, 1,024 features,
+# 10,240 individuals, 50 generations, program sizes 127 / 1,023 / 2,047, the
+# paper's own loop (every individual mutated once, random step), FP32.
+for _k in (127, 1023, 2047):
+    WORKLOADS[f"paper_shape_k{_k}"] = Workload(
+        f"paper_shape_k{_k}", 102_400, 0, 1024, 10_240, 10_240, 50, "fp32", genome_len=_k,
+        tournament_size=0, p_crossover=0.0, mutation_step=0.1,
+        notes="U[-1,1] features, sparse cubic target; mutate-all loop, random mutation step")
+
 
 
 def _split(X, y, n_train):
@@ -135,6 +144,15 @@ def batched_runs(runs=256, n_lo=200, n_hi=50_000, seed_offset=0, max_total=None)
         y = sparse_cubic(rng, X)
         out.append(_split(X, y, n))
     return out
+
+
+def paper_shape(n_train=102_400, n_features=1024, seed_offset=0) -> Dataset:
+    """Stand-in for the speed-up study's dummy data: U[-1, 1] features and a
+    sparse cubic target (the paper does not state its distribution)."""
+    rng = np.random.default_rng(BASE_SEED + 10 * 5 + seed_offset)
+    X = rng.uniform(-1.0, 1.0, size=(n_train, n_features))
+    y = sparse_cubic(rng, X)
+    return Dataset(X, y, np.zeros((0, n_features)), np.zeros(0))
 
 
 def evolution_seed(workload_index: int) -> int:
