@@ -161,6 +161,7 @@ def bench_single(args, wl, data, seed) -> dict:
     R.eval_population()
     torch.cuda.synchronize()
     eval_ms = (time.perf_counter() - e0) * 1e3
+    eval_stages = R.time_eval()
 
     # per-stage HIP-event timing of the generation's kernels on the library stream
     ng = min(args.stage_gens, G)
@@ -202,6 +203,7 @@ def bench_single(args, wl, data, seed) -> dict:
                      "distinct_pool_rows": float(u[:, 1].mean())},
         "stages_ms": {k: round(v, 5) for k, v in stages.items()},
         "eval_population_ms": eval_ms,
+        "eval_stages_ms": {k: round(v, 5) for k, v in eval_stages.items()},
         "generation_elements_per_s": gen_rate,
         "final_best_train_rmse": float(final["best_train_rmse"]),
         "final_best_test_rmse": float(final["best_test_rmse"]),
