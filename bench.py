@@ -76,13 +76,24 @@ def traffic_from_profile(per_launch_alg: float):
     return float(t.group(1))
 
 
-def cpu_baseline(workload, data, G: int, seed: int, frac: int = 4, g_sample: int = 30):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(workload, data, G: int, seed: int, frac: int = 4, g_sample: int = 30, threads: int = 0):
     """The FP64 CPU oracle on a case slice of the same workload (all of m, r,
     k; 1/frac of the train and test cases), timed for initialisation and
-    g_sample generations on every host core, then scaled linearly in the
-    number of cases to a full step."""
+    g_sample generations on `threads` host cores (0: every core), then
+    scaled linearly in the number of cases to a full step."""
     from oracle import oracle as orc
-    cores = len(os.sched_getaffinity(0))
+    all_cores = len(os.sched_getaffinity(0))
+    cores = threads or all_cores
     orc.set_threads(cores)
     ntr = data.X_train.shape[0] // frac
     nte = data.X_test.shape[0] // frac
@@ -105,6 +116,7 @@ def cpu_baseline(workload, data, G: int, seed: int, frac: int = 4, g_sample: int
     t_step = scale * ((t1 - t0) + (t2 - t1) / g_sample * G)
     n_all = data.X_train.shape[0] + data.X_test.shape[0]
     value = workload.pop_size * n_all * G / t_step
+    orc.set_threads(all_cores)
     sample = (f"FP64 oracle, {cores} threads: case slice 1/{frac} ({ntr} train + {nte} test), "
               f"m=r={workload.pop_size}, init {t1 - t0:.2f} s + {g_sample} generations "
               f"{t2 - t1:.2f} s, scaled linearly in cases to init + {G} generations")
@@ -175,6 +187,20 @@ def bench_single(args, wl, data, seed) -> dict:
     achieved = per_launch / (stages["vary_ms"] * 1e-3) / 1e9
     traffic = traffic_from_profile(per_launch) if wl.name == "single_fp32_100k" else None
     gen_rate = m * n_all / (stages["generation_ms"] * 1e-3)
+    # per-generation distribution: one graph launch per generation, HIP
+    # events on the library stream around each
+    per_gen = []
+    n_single = max(1, min(50, G - R.current_generation()))
+    if R.current_generation() + n_single > G:  # no generation left: restart the run
+        R.eval_population()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(n_single)]
+    for a, b in ev:
+        a.record(R.stream)
+        R.generation(1, stats=False)
+        b.record(R.stream)
+    torch.cuda.synchronize()
+    per_gen = np.array([a.elapsed_time(b) for a, b in ev])
     R.close()
 
     out = {
@@ -205,6 +231,8 @@ def bench_single(args, wl, data, seed) -> dict:
         "eval_population_ms": eval_ms,
         "eval_stages_ms": {k: round(v, 5) for k, v in eval_stages.items()},
         "generation_elements_per_s": gen_rate,
+        "generation_ms_single_launches": {"mean": float(per_gen.mean()), "p50": float(np.median(per_gen)),
+                                          "max": float(per_gen.max()), "n": int(per_gen.size)},
         "final_best_train_rmse": float(final["best_train_rmse"]),
         "final_best_test_rmse": float(final["best_test_rmse"]),
     }
@@ -215,6 +243,11 @@ def bench_single(args, wl, data, seed) -> dict:
         cb = cpu_baseline(wl, data, G, seed, frac=frac)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         out["cpu_baseline"]["gen_elements_per_s"] = cb["gen_elements_per_s"]
+        out["cpu_baseline"]["cpu_model"] = cpu_model()
+        # the sequential reference point (the paper compares with a sequential
+        # CPU implementation): one thread on a smaller slice
+        c1 = cpu_baseline(wl, data, G, seed, frac=frac * 4 if frac > 1 else 1, g_sample=10, threads=1)
+        out["cpu_baseline"]["one_thread"] = {k: c1[k] for k in ("value", "gen_elements_per_s", "sample")}
     return out
 
 

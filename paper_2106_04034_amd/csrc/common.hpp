@@ -24,7 +24,8 @@ constexpr int kSegPad = 64;
 constexpr int kWave = 64;
 constexpr int kMaxTournament = 64;
 // Deepest stack (values, top included) a compiled genome may need: the
-// interpreter keeps depth - 1 values per lane in at most 64 KiB of LDS.
+// interpreter keeps the top two values in registers and depth - 2 per lane
+// in LDS, at most 64 KiB for one wave.
 constexpr int kMaxStack = 65;
 
 // Compiled genome op word: bits 0..2 kind, bits 3..15 stack depth before
@@ -141,8 +142,9 @@ hipError_t launch_set_state(const RunDev* d_runs, int32_t n_runs, int32_t word, 
                             hipStream_t s);
 hipError_t launch_genome(const RunDev* d_runs, const Params& p, hipStream_t s);
 hipError_t launch_compile(const RunDev* d_runs, const Params& p, hipStream_t s);
+// slots: stack values per lane kept in LDS (deepest stack - 2, at least 1).
 hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_blocks, int max_features,
-                            int depth, hipStream_t s);
+                            int slots, hipStream_t s);
 hipError_t launch_vary(const RunDev* d_runs, const Params& p, const VaryLaunch& lc, bool rows_only,
                        hipStream_t s);
 hipError_t launch_fitness(const RunDev* d_runs, const Params& p, bool init, hipStream_t s);
@@ -154,7 +156,7 @@ hipError_t launch_transpose(const double* X, int64_t n, int32_t l, double* Xfm, 
 hipError_t launch_interpret_list(const int32_t* ops, const double* opv, const int32_t* nops,
                                  int32_t k, const int32_t* prog, const int32_t* squash,
                                  int32_t nprog, const double* Xfm, int64_t ld, int64_t n,
-                                 double* out, int depth, hipStream_t s);
+                                 double* out, int slots, hipStream_t s);
 struct ReplayNode {
   int32_t op;     // 0 mutation, 1 crossover, 2 copy
   int32_t a, b;   // source slots (previous generation); b = -1 unless crossover

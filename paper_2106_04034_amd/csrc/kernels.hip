@@ -29,6 +29,8 @@
 #include <float.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace gsgp {
@@ -53,6 +55,30 @@ struct VecOf<double> {
 constexpr double kFltMax = 3.4028234663852886e38;  // largest finite binary32 value
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Buffers reach the kernels through RunDev as generic pointers; casting to
+// the global address space lets the compiler emit global (not flat) memory
+// instructions, the constant address space gives scalar loads for data no
+// kernel in flight writes (records, compiled programs, generation counter),
+// and the local address space gives LDS instructions for shared memory.
+#define GSGP_GLOBAL __attribute__((address_space(1)))
+#define GSGP_CONST __attribute__((address_space(4)))
+#define GSGP_LDS __attribute__((address_space(3)))
+
+template <typename VT>
+__device__ __forceinline__ VT gload(const void* p) {
+  return *(const GSGP_GLOBAL VT*)p;
+}
+
+template <typename VT>
+__device__ __forceinline__ void gstore_nt(const VT& v, void* p) {
+  __builtin_nontemporal_store(v, (GSGP_GLOBAL VT*)p);
+}
+
+template <typename X>
+__device__ __forceinline__ X cload(const X* p) {
+  return *(const GSGP_CONST X*)p;
+}
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011): ten rounds of two
@@ -226,58 +252,90 @@ __global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs
 }
 
 // Evaluate one compiled program on V cases per lane (Section 2.2
-// "Interpreter").  The op stream is wave-uniform.  tos holds the top of the
-// stack; slot d of the rest lives at stk[(d * V + v) * 64 + lane].  The value
-// of the program is the output of its last function (the Out register), 0.0
-// if none runs.
-template <int V>
-__device__ __forceinline__ void eval_program(const int32_t* __restrict__ ops,
-                                             const double* __restrict__ opv, int n,
-                                             const double* __restrict__ X, int64_t ld,
-                                             const int64_t (&col)[V], const bool (&ok)[V],
-                                             double* __restrict__ stk, int lane, double (&out)[V]) {
-  double tos[V];
+// "Interpreter").  The op stream is wave-uniform and read with scalar loads,
+// eight ops per batch.  Stack element i of depth d (0 = bottom) lives in
+// registers for the top two (tos = d-1, nos = d-2) and in LDS below them,
+// at stk[(i * V + v) * 64 + lane]; a function reads its new second operand
+// from LDS only after it has produced its result, so the LDS latency falls
+// outside the op's dependency chain.  The value of the program is the
+// output of its last function (the Out register), 0.0 if none runs.
+// X is the feature-major case block: in LDS (XLDS, ld = cases per block) or
+// in global memory (lanes whose column is out of range read nothing).
+template <int V, bool XLDS>
+__device__ __forceinline__ void eval_program(const int32_t* ops, const double* opv, int n, const double* X,
+                                             int64_t ld, const int64_t (&col)[V], const bool (&ok)[V],
+                                             double* stk_lds, int lane, double (&out)[V]) {
+  constexpr int kBatch = 8;
+  const GSGP_CONST int32_t* cops = (const GSGP_CONST int32_t*)ops;
+  const GSGP_CONST double* copv = (const GSGP_CONST double*)opv;
+  GSGP_LDS double* stk = (GSGP_LDS double*)stk_lds;
+  double tos[V], nos[V];
 #pragma unroll
-  for (int v = 0; v < V; ++v) tos[v] = 0.0;
-  for (int j = 0; j < n; ++j) {
-    const int w = uni(ops[j]);
-    const int kind = w & 7;
-    const int d = (w >> 3) & 0x1FFF;
-    if (kind <= kPushConst) {
-      if (d > 0) {
+  for (int v = 0; v < V; ++v) {
+    tos[v] = 0.0;
+    nos[v] = 0.0;
+  }
+  for (int j0 = 0; j0 < n; j0 += kBatch) {
+    int wv[kBatch];
+    double cv[kBatch];
 #pragma unroll
-        for (int v = 0; v < V; ++v) stk[((d - 1) * V + v) * kWave + lane] = tos[v];
-      }
-      if (kind == kPushFeature) {
-        const int64_t base = (int64_t)((uint32_t)w >> 16) * ld;
+    for (int u = 0; u < kBatch; ++u) {
+      const int j = j0 + u < n ? j0 + u : n - 1;  // stay inside this program's ops
+      wv[u] = cops[j];
+      cv[u] = copv[j];
+    }
 #pragma unroll
-        for (int v = 0; v < V; ++v) tos[v] = ok[v] ? X[base + col[v]] : 0.0;
+    for (int u = 0; u < kBatch; ++u) {
+      if (j0 + u >= n) break;
+      const int w = wv[u];
+      const int kind = w & 7;
+      const int d = (w >> 3) & 0x1FFF;  // stack depth before the op
+      if (kind <= kPushConst) {
+        if (d >= 2) {
+#pragma unroll
+          for (int v = 0; v < V; ++v) stk[((d - 2) * V + v) * kWave + lane] = nos[v];
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) nos[v] = tos[v];
+        if (kind == kPushFeature) {
+          const int f = (int)((uint32_t)w >> 16);
+          if constexpr (XLDS) {
+            const GSGP_LDS double* xl = (const GSGP_LDS double*)X + f * (int)ld;
+#pragma unroll
+            for (int v = 0; v < V; ++v) tos[v] = xl[(int)col[v]];
+          } else {
+            const GSGP_GLOBAL double* xg = (const GSGP_GLOBAL double*)X + (int64_t)f * ld;
+#pragma unroll
+            for (int v = 0; v < V; ++v) tos[v] = ok[v] ? xg[col[v]] : 0.0;
+          }
+        } else {
+#pragma unroll
+          for (int v = 0; v < V; ++v) tos[v] = cv[u];
+        }
       } else {
-        const double c = opv[j];
+        // element d-2 (nos) op element d-1 (tos)
+        if (kind == kAdd) {
 #pragma unroll
-        for (int v = 0; v < V; ++v) tos[v] = c;
-      }
-    } else {
-      double a[V];
+          for (int v = 0; v < V; ++v) tos[v] = nos[v] + tos[v];
+        } else if (kind == kSub) {
 #pragma unroll
-      for (int v = 0; v < V; ++v) a[v] = stk[((d - 2) * V + v) * kWave + lane];
-      if (kind == kAdd) {
+          for (int v = 0; v < V; ++v) tos[v] = nos[v] - tos[v];
+        } else if (kind == kMul) {
 #pragma unroll
-        for (int v = 0; v < V; ++v) tos[v] = a[v] + tos[v];
-      } else if (kind == kSub) {
+          for (int v = 0; v < V; ++v) tos[v] = nos[v] * tos[v];
+        } else {
 #pragma unroll
-        for (int v = 0; v < V; ++v) tos[v] = a[v] - tos[v];
-      } else if (kind == kMul) {
+          for (int v = 0; v < V; ++v) tos[v] = (fabs(tos[v]) < 1e-6) ? 1.0 : nos[v] / tos[v];
+        }
+        // Every operand is finite (finite features and constants, results
+        // clamped here, protected division), so min/max clamp exactly as a
+        // compare-and-select would.
 #pragma unroll
-        for (int v = 0; v < V; ++v) tos[v] = a[v] * tos[v];
-      } else {
+        for (int v = 0; v < V; ++v) tos[v] = fmin(fmax(tos[v], -kFltMax), kFltMax);
+        if (d >= 3) {
 #pragma unroll
-        for (int v = 0; v < V; ++v) tos[v] = (fabs(tos[v]) < 1e-6) ? 1.0 : a[v] / tos[v];
-      }
-#pragma unroll
-      for (int v = 0; v < V; ++v) {
-        const double r = tos[v];
-        tos[v] = r > kFltMax ? kFltMax : (r < -kFltMax ? -kFltMax : r);
+          for (int v = 0; v < V; ++v) nos[v] = stk[((d - 3) * V + v) * kWave + lane];
+        }
       }
     }
   }
@@ -297,7 +355,7 @@ constexpr int kInterpProgsPerWave = 4;   // programs each wave interprets on its
 // Section 2) before storage.  Padding columns are written as exact zeros.
 template <typename T, bool XLDS>
 __global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ runs, Params p, int32_t pgroups,
-                                                   int depth, int32_t xtile_doubles) {
+                                                   int slots, int32_t xtile_doubles) {
   extern __shared__ double lds[];
   const int lane = threadIdx.x & 63;
   const int wave = uni(threadIdx.x >> 6);
@@ -309,12 +367,12 @@ __global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ ru
   const int64_t cb = cbg - R.cblk0;
   const int64_t ld = R.ld;
   const int rows = p.m + p.r;
-  double* stk = lds + xtile_doubles + (int64_t)wave * depth * kInterpV * kWave;
+  double* stk = lds + xtile_doubles + wave * slots * kInterpV * kWave;
   if constexpr (XLDS) {
     for (int idx = threadIdx.x; idx < R.l * kInterpTile; idx += blockDim.x) {
       const int f = idx / kInterpTile;
       const int64_t gc = cb * kInterpTile + (idx - f * kInterpTile);
-      lds[idx] = gc < ld ? R.X[(int64_t)f * ld + gc] : 0.0;
+      lds[idx] = gc < ld ? ((const GSGP_GLOBAL double*)R.X)[(int64_t)f * ld + gc] : 0.0;
     }
     __syncthreads();
   }
@@ -331,11 +389,11 @@ __global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ ru
     if (prog >= rows) break;
     double out[kInterpV];
     if constexpr (XLDS)
-      eval_program<kInterpV>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k, uni(R.nops[prog]), lds,
-                             kInterpTile, xcol, ok, stk, lane, out);
+      eval_program<kInterpV, true>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k,
+                                   uni(cload(&R.nops[prog])), lds, kInterpTile, xcol, ok, stk, lane, out);
     else
-      eval_program<kInterpV>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k, uni(R.nops[prog]), R.X,
-                             ld, xcol, ok, stk, lane, out);
+      eval_program<kInterpV, false>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k,
+                                    uni(cload(&R.nops[prog])), R.X, ld, xcol, ok, stk, lane, out);
     const bool pool = prog >= p.m;
     T* dst = pool ? (T*)R.sigR : (T*)R.S[0];
     const int64_t nrows = pool ? p.r : p.m;
@@ -384,61 +442,53 @@ __device__ __forceinline__ void wave_sum_kahan(float& s, float& c) {
 }
 
 // Sum over one chunk of (o - t)^2 in the canonical order: each lane adds its
-// elements in address order, then the wave butterfly.  FP32 forms fall back
-// to FP64 when a square overflows; the fallback re-reads the chunk of the
-// row (`row`, already stored by this wave) and of the target (`tgt`) so the
-// offspring values need not stay live across the reduction.
-template <typename T, int PREC, int NJ, typename VT>
-__device__ __forceinline__ double chunk_sse(const VT (&o)[NJ], const VT (&t)[NJ], const bool (&ok)[NJ],
-                                            const T* row, const T* tgt, int lane) {
-  constexpr int N = VecOf<T>::N;
-  if constexpr (PREC == GSGP_FP64) {
-    double s = 0.0;
+// elements in address order (LaneSse, fed one 16-byte vector at a time as
+// the offspring values are formed), then the wave butterfly (sse_finish).
+// FP32 forms fall back to FP64 when a square overflows; the fallback
+// re-reads the chunk of the row (`row`, already stored by this wave) and of
+// the target (`tgt`) so the offspring values need not stay live across the
+// reduction.
+template <typename T, int PREC>
+struct LaneSse {
+  typedef typename std::conditional<PREC == GSGP_FP64, double, float>::type A;
+  A s = 0, c = 0;
+  template <typename VT>
+  __device__ __forceinline__ void add(const VT& o, const VT& t) {
+    constexpr int N = VecOf<T>::N;
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      if (!ok[j]) continue;
-#pragma unroll
-      for (int c = 0; c < N; ++c) {
-        const double e = o[j][c] - t[j][c];
+    for (int k = 0; k < N; ++k) {
+      const A e = (A)o[k] - (A)t[k];
+      if constexpr (PREC == GSGP_FP32_KAHAN) {
+        const A y = e * e - c;
+        const A u = s + y;
+        c = (u - s) - y;
+        s = u;
+      } else {
         s += e * e;
       }
     }
-    return wave_sum(s);
+  }
+};
+
+template <typename T, int PREC, int NJ>
+__device__ __forceinline__ double sse_finish(LaneSse<T, PREC> acc, const bool (&ok)[NJ], const T* row,
+                                             const T* tgt, int lane) {
+  constexpr int N = VecOf<T>::N;
+  if constexpr (PREC == GSGP_FP64) {
+    return wave_sum(acc.s);
   } else {
     double total;
     if constexpr (PREC == GSGP_FP32) {
-      float s = 0.0f;
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        if (!ok[j]) continue;
-#pragma unroll
-        for (int c = 0; c < N; ++c) {
-          const float e = o[j][c] - t[j][c];
-          s += e * e;
-        }
-      }
-      s = wave_sum(s);
-      total = (double)s;
+      total = (double)wave_sum(acc.s);
     } else {
-      float s = 0.0f, comp = 0.0f;
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        if (!ok[j]) continue;
-#pragma unroll
-        for (int c = 0; c < N; ++c) {
-          const float e = o[j][c] - t[j][c];
-          const float y = e * e - comp;
-          const float u = s + y;
-          comp = (u - s) - y;
-          s = u;
-        }
-      }
-      wave_sum_kahan(s, comp);
-      total = (double)s - (double)comp;
+      wave_sum_kahan(acc.s, acc.c);
+      total = (double)acc.s - (double)acc.c;
     }
     if (!isfinite(total)) {
-      // make this wave's own stores of the row visible to its loads
-      __atomic_thread_fence(__ATOMIC_SEQ_CST);
+      // Each lane re-reads exactly the elements it stored itself; a
+      // wavefront-scope fence orders those accesses without the L2
+      // write-back and invalidation of a device- or system-scope fence.
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       double s = 0.0;
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
@@ -456,26 +506,14 @@ __device__ __forceinline__ double chunk_sse(const VT (&o)[NJ], const VT (&t)[NJ]
   }
 }
 
-// Buffers reach the kernels through RunDev as generic pointers; casting to
-// the global address space lets the compiler emit global (not flat) memory
-// instructions, and the constant address space gives scalar loads for data
-// no kernel in flight writes (records, generation counter).
-#define GSGP_GLOBAL __attribute__((address_space(1)))
-#define GSGP_CONST __attribute__((address_space(4)))
-
-template <typename VT>
-__device__ __forceinline__ VT gload(const void* p) {
-  return *(const GSGP_GLOBAL VT*)p;
-}
-
-template <typename VT>
-__device__ __forceinline__ void gstore_nt(const VT& v, void* p) {
-  __builtin_nontemporal_store(v, (GSGP_GLOBAL VT*)p);
-}
-
-template <typename X>
-__device__ __forceinline__ X cload(const X* p) {
-  return *(const GSGP_CONST X*)p;
+template <typename T, int PREC, int NJ, typename VT>
+__device__ __forceinline__ double chunk_sse(const VT (&o)[NJ], const VT (&t)[NJ], const bool (&ok)[NJ],
+                                            const T* row, const T* tgt, int lane) {
+  LaneSse<T, PREC> acc;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j)
+    if (ok[j]) acc.add(o[j], t[j]);
+  return sse_finish<T, PREC, NJ>(acc, ok, row, tgt, lane);
 }
 
 // One offspring's operands for one chunk.  Mutation reads S[p1], sR[r1],
@@ -516,30 +554,31 @@ __device__ __forceinline__ void vary_offspring(const gsgp_record* rc, const T* S
       z[j] = VT(0);
     }
   }
-  VT o[NJ];
+  // Form, clamp, store and accumulate one 16-byte vector at a time, so the
+  // operands of a vector die as soon as its offspring value is stored.
+  LaneSse<T, PREC> acc;
+  auto emit = [&](int j, VT o) {
+    if constexpr (PREC != GSGP_FP64) {
+      // a convex combination of two values near +-FLT_MAX can round past it;
+      // operands are finite, so a median-of-three clamps exactly
+#pragma unroll
+      for (int c = 0; c < N; ++c) o[c] = __builtin_amdgcn_fmed3f(o[c], (T)-kFltMax, (T)kFltMax);
+    }
+    if (ok[j]) {
+      gstore_nt<VT>(o, dst + j * kWave * N + lane * N);
+      acc.add(o, t[j]);
+    }
+  };
   if (op == 1) {
     // GSC: O = S[p1] * sR[r1] + S[p2] * (1 - sR[r1])
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) o[j] = x[j] * z[j] + y[j] * ((T)1 - z[j]);
+    for (int j = 0; j < NJ; ++j) emit(j, x[j] * z[j] + y[j] * ((T)1 - z[j]));
   } else {
     // GSM: O = S[p1] + ms * (sR[r1] - sR[r2])
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) o[j] = x[j] + ms * (y[j] - z[j]);
+    for (int j = 0; j < NJ; ++j) emit(j, x[j] + ms * (y[j] - z[j]));
   }
-  if constexpr (PREC != GSGP_FP64) {
-    // a convex combination of two values near +-FLT_MAX can round past it
-#pragma unroll
-    for (int j = 0; j < NJ; ++j)
-#pragma unroll
-      for (int c = 0; c < N; ++c) {
-        const T v = o[j][c];
-        o[j][c] = v > (T)kFltMax ? (T)kFltMax : (v < (T)-kFltMax ? (T)-kFltMax : v);
-      }
-  }
-#pragma unroll
-  for (int j = 0; j < NJ; ++j)
-    if (ok[j]) gstore_nt<VT>(o[j], dst + j * kWave * N + lane * N);
-  const double sse = chunk_sse<T, PREC, NJ, VT>(o, t, ok, dst, tgt, lane);
+  const double sse = sse_finish<T, PREC, NJ>(acc, ok, dst, tgt, lane);
   if (lane == 0) *part_out = sse;
 }
 
@@ -611,7 +650,7 @@ __device__ __forceinline__ void vary_task(const RunDev& R, const Params& p, cons
 // 16-byte stores and writes the chunk's sum of squared residuals.  With
 // ROWS the kernel only forms the partial sums of the current population
 // (generation-0 fitness).
-template <typename T, int PREC, bool ROWS>
+template <typename T, int PREC, bool ROWS, bool LOOP>
 __global__ __launch_bounds__(512) void k_vary(const RunDev* __restrict__ runs, Params p, VaryLaunch lc) {
   constexpr int kChunk = chunk_cases(sizeof(T));
   const int lane = threadIdx.x & 63;
@@ -620,8 +659,11 @@ __global__ __launch_bounds__(512) void k_vary(const RunDev* __restrict__ runs, P
   // contiguous range of tasks.  remap 2: XCD x takes the x-th group of
   // `ogroups` tasks (one chunk) of every run of 8 chunks, so the XCDs sweep
   // the rows side by side through an 8-chunk window.
+  // LOOP: a persistent grid, blocks sweep the tasks; otherwise the grid
+  // covers every task in one sweep and the loop body runs once (no values
+  // hoisted across iterations, fewer registers).
   const int64_t xcd = blockIdx.x & 7, slot = blockIdx.x >> 3, per = lc.grid >> 3;
-  for (int64_t it = 0;; ++it) {
+  for (int64_t it = 0; LOOP || it == 0; ++it) {
     int64_t task;
     if (lc.remap == 2) {
       const int64_t q = slot + it * per;
@@ -986,7 +1028,7 @@ __global__ __launch_bounds__(256) void k_interpret_list(const int32_t* __restric
                                                         const int32_t* __restrict__ squash,
                                                         int32_t nprog, const double* __restrict__ Xfm,
                                                         int64_t ld, int64_t n, double* __restrict__ out,
-                                                        int depth, int64_t total) {
+                                                        int slots, int64_t total) {
   extern __shared__ double lds[];
   const int lane = threadIdx.x & 63;
   const int wave = uni(threadIdx.x >> 6);
@@ -1003,9 +1045,9 @@ __global__ __launch_bounds__(256) void k_interpret_list(const int32_t* __restric
     ok[v] = col[v] < ld;
   }
   double val[kInterpV];
-  double* stk = lds + (int64_t)wave * depth * kInterpV * kWave;
-  eval_program<kInterpV>(ops + (int64_t)pr * k, opv + (int64_t)pr * k, uni(nops[pr]), Xfm, ld, col, ok,
-                         stk, lane, val);  // column index doubles as the X offset here
+  double* stk = lds + wave * slots * kInterpV * kWave;
+  eval_program<kInterpV, false>(ops + (int64_t)pr * k, opv + (int64_t)pr * k, uni(nops[pr]), Xfm, ld, col, ok,
+                                stk, lane, val);  // column index doubles as the X offset here
   const bool sq = squash[j] != 0;
 #pragma unroll
   for (int v = 0; v < kInterpV; ++v) {
@@ -1045,9 +1087,9 @@ __global__ void k_set_state(const RunDev* __restrict__ runs, int32_t n_runs, int
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 // Waves per interpreter block so that the LDS stacks of one block stay
-// within 64 KiB: each wave needs depth * kInterpV * 64 doubles.
-inline int interp_waves(int depth) {
-  const int per_wave = depth * kInterpV * kWave * (int)sizeof(double);
+// within 64 KiB: each wave needs slots * kInterpV * 64 doubles.
+inline int interp_waves(int slots) {
+  const int per_wave = slots * kInterpV * kWave * (int)sizeof(double);
   int w = 65536 / per_wave;
   return w < 1 ? 1 : (w > 4 ? 4 : w);
 }
@@ -1088,18 +1130,18 @@ hipError_t launch_compile(const RunDev* d_runs, const Params& p, hipStream_t s) 
 }
 
 hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_blocks, int max_features,
-                            int depth, hipStream_t s) {
-  if (depth < 1) depth = 1;
+                            int slots, hipStream_t s) {
+  if (slots < 1) slots = 1;
   // LDS budget 64 KiB: the features of 128 cases (when staged) plus one
   // stack column block per wave.
-  const int64_t stack_per_wave = (int64_t)depth * kInterpV * kWave * sizeof(double);
+  const int64_t stack_per_wave = (int64_t)slots * kInterpV * kWave * sizeof(double);
   const int64_t xtile = (int64_t)max_features * kInterpTile * sizeof(double);
   int waves = 4;
   bool xlds = true;
   while (waves > 1 && xtile + waves * stack_per_wave > 65536) --waves;
   if (xtile + waves * stack_per_wave > 65536) {
     xlds = false;
-    waves = interp_waves(depth);
+    waves = interp_waves(slots);
   }
   const int rows = p.m + p.r;
   const int32_t pgroups = (rows + waves * kInterpProgsPerWave - 1) / (waves * kInterpProgsPerWave);
@@ -1108,40 +1150,52 @@ hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_
   const dim3 grid((unsigned)(case_blocks * pgroups)), block(waves * kWave);
   if (p.precision == GSGP_FP64) {
     if (xlds)
-      hipLaunchKernelGGL((k_interpret<double, true>), grid, block, shmem, s, d_runs, p, pgroups, depth, xdoubles);
+      hipLaunchKernelGGL((k_interpret<double, true>), grid, block, shmem, s, d_runs, p, pgroups, slots, xdoubles);
     else
-      hipLaunchKernelGGL((k_interpret<double, false>), grid, block, shmem, s, d_runs, p, pgroups, depth, xdoubles);
+      hipLaunchKernelGGL((k_interpret<double, false>), grid, block, shmem, s, d_runs, p, pgroups, slots, xdoubles);
   } else {
     if (xlds)
-      hipLaunchKernelGGL((k_interpret<float, true>), grid, block, shmem, s, d_runs, p, pgroups, depth, xdoubles);
+      hipLaunchKernelGGL((k_interpret<float, true>), grid, block, shmem, s, d_runs, p, pgroups, slots, xdoubles);
     else
-      hipLaunchKernelGGL((k_interpret<float, false>), grid, block, shmem, s, d_runs, p, pgroups, depth, xdoubles);
+      hipLaunchKernelGGL((k_interpret<float, false>), grid, block, shmem, s, d_runs, p, pgroups, slots, xdoubles);
   }
   return hipGetLastError();
+}
+
+template <typename T, int PREC>
+void launch_vary_as(const RunDev* d_runs, const Params& p, const VaryLaunch& lc, bool rows_only, bool one_shot,
+                    dim3 grid, dim3 block, hipStream_t s) {
+  if (rows_only) {
+    if (one_shot)
+      hipLaunchKernelGGL((k_vary<T, PREC, true, false>), grid, block, 0, s, d_runs, p, lc);
+    else
+      hipLaunchKernelGGL((k_vary<T, PREC, true, true>), grid, block, 0, s, d_runs, p, lc);
+  } else {
+    if (one_shot)
+      hipLaunchKernelGGL((k_vary<T, PREC, false, false>), grid, block, 0, s, d_runs, p, lc);
+    else
+      hipLaunchKernelGGL((k_vary<T, PREC, false, true>), grid, block, 0, s, d_runs, p, lc);
+  }
 }
 
 hipError_t launch_vary(const RunDev* d_runs, const Params& p, const VaryLaunch& lc, bool rows_only,
                        hipStream_t s) {
   if (lc.total_tasks <= 0) return hipSuccess;
   const dim3 grid((unsigned)lc.grid), block(lc.waves * kWave);
+  // every task in the first sweep of the grid: the loop-free instance
+  const int64_t sweep = lc.remap == 2 ? (lc.total_tasks + 8 * (int64_t)lc.ogroups - 1) / (8 * (int64_t)lc.ogroups) *
+                                            (8 * (int64_t)lc.ogroups)
+                                      : lc.total_tasks;
+  const bool one_shot = lc.grid >= sweep;
   switch (p.precision) {
     case GSGP_FP64:
-      if (rows_only)
-        hipLaunchKernelGGL((k_vary<double, GSGP_FP64, true>), grid, block, 0, s, d_runs, p, lc);
-      else
-        hipLaunchKernelGGL((k_vary<double, GSGP_FP64, false>), grid, block, 0, s, d_runs, p, lc);
+      launch_vary_as<double, GSGP_FP64>(d_runs, p, lc, rows_only, one_shot, grid, block, s);
       break;
     case GSGP_FP32:
-      if (rows_only)
-        hipLaunchKernelGGL((k_vary<float, GSGP_FP32, true>), grid, block, 0, s, d_runs, p, lc);
-      else
-        hipLaunchKernelGGL((k_vary<float, GSGP_FP32, false>), grid, block, 0, s, d_runs, p, lc);
+      launch_vary_as<float, GSGP_FP32>(d_runs, p, lc, rows_only, one_shot, grid, block, s);
       break;
     default:
-      if (rows_only)
-        hipLaunchKernelGGL((k_vary<float, GSGP_FP32_KAHAN, true>), grid, block, 0, s, d_runs, p, lc);
-      else
-        hipLaunchKernelGGL((k_vary<float, GSGP_FP32_KAHAN, false>), grid, block, 0, s, d_runs, p, lc);
+      launch_vary_as<float, GSGP_FP32_KAHAN>(d_runs, p, lc, rows_only, one_shot, grid, block, s);
       break;
   }
   return hipGetLastError();
@@ -1182,15 +1236,15 @@ hipError_t launch_transpose(const double* X, int64_t n, int32_t l, double* Xfm, 
 hipError_t launch_interpret_list(const int32_t* ops, const double* opv, const int32_t* nops,
                                  int32_t k, const int32_t* prog, const int32_t* squash,
                                  int32_t nprog, const double* Xfm, int64_t ld, int64_t n,
-                                 double* out, int depth, hipStream_t s) {
+                                 double* out, int slots, hipStream_t s) {
   if (nprog <= 0) return hipSuccess;
-  if (depth < 1) depth = 1;
+  if (slots < 1) slots = 1;
   const int64_t cblocks = (ld + kWave * kInterpV - 1) / (kWave * kInterpV);
   const int64_t total = cblocks * nprog;
-  const int waves = interp_waves(depth);
-  const size_t shmem = (size_t)waves * depth * kInterpV * kWave * sizeof(double);
+  const int waves = interp_waves(slots);
+  const size_t shmem = (size_t)waves * slots * kInterpV * kWave * sizeof(double);
   hipLaunchKernelGGL(k_interpret_list, dim3(blocks_for(total, waves)), dim3(waves * kWave),
-                     shmem, s, ops, opv, nops, k, prog, squash, nprog, Xfm, ld, n, out, depth, total);
+                     shmem, s, ops, opv, nops, k, prog, squash, nprog, Xfm, ld, n, out, slots, total);
   return hipGetLastError();
 }
 

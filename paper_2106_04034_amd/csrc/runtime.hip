@@ -165,7 +165,7 @@ struct gsgp_handle {
   int64_t interp_tasks = 0;  // 128-case blocks over all runs
   int32_t max_features = 0;
   int32_t surv_blocks = 0;
-  int32_t depth = 1;
+  int32_t slots = 1;         // interpreter stack values per lane in LDS
   int32_t max_blocks = 0;
   int32_t gen = 0;
   bool evaluated = false;
@@ -522,8 +522,8 @@ gsgp_status eval_impl(gsgp_handle* h, const int32_t* h_codes, const double* h_co
     h->evaluated = false;
     return fail(GSGP_ERR_UNSUPPORTED, "a genome needs a stack of %d values; at most %d are supported", deepest, kMaxStack);
   }
-  h->depth = std::max(1, deepest - 1);
-  HIPCHK(h, launch_interpret(h->runs_d, p, h->interp_tasks, h->max_features, h->depth, h->stream));
+  h->slots = std::max(1, deepest - 2);  // the top two values live in registers
+  HIPCHK(h, launch_interpret(h->runs_d, p, h->interp_tasks, h->max_features, h->slots, h->stream));
   if (ev) HIPCHK(h, hipEventRecord(ev[2], h->stream));
   HIPCHK(h, launch_vary(h->runs_d, p, h->rows, true, h->stream));
   HIPCHK(h, launch_fitness(h->runs_d, p, true, h->stream));
@@ -1011,9 +1011,9 @@ gsgp_status gsgp_reconstruct(gsgp_handle* h, int32_t run, int32_t gen, int32_t i
   const int32_t* d_sqp = d_progp + np + 1;
   HIPCHK(h, launch_transpose(d_X, n, R.l, Xfm, L.ld, h->stream));
   HIPCHK(h, launch_interpret_list(R.ops, R.opv, R.nops, h->cfg.genome_len, d_prog0, d_sq0, (int32_t)n0, Xfm, L.ld, n,
-                                  bufA, h->depth, h->stream));
+                                  bufA, h->slots, h->stream));
   HIPCHK(h, launch_interpret_list(R.ops, R.opv, R.nops, h->cfg.genome_len, d_progp, d_sqp, (int32_t)np, Xfm, L.ld, n,
-                                  pool, h->depth, h->stream));
+                                  pool, h->slots, h->stream));
   double* cur = bufA;
   double* nxt = bufB;
   for (int32_t g = 1; g <= gen; ++g) {

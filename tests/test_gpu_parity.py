@@ -196,6 +196,58 @@ def test_fp32_forms_follow_oracle_lineage(precision):
     R.close()
 
 
+@pytest.mark.parametrize("precision,tsize,pxo", [(gsgp.FP32, 4, 0.5), (gsgp.FP32_KAHAN, 0, 0.0)])
+def test_fp32_overflow_fallback_follows_oracle(precision, tsize, pxo):
+    """Programs whose semantics saturate at +-FLT_MAX make the FP32 squares
+    overflow, so the FP32 forms take their FP64 fallback (re-reading the
+    stored chunk) at generation 0 and in the variation kernel.  Genomes are
+    written here (x0 divided seven times by +-1.5e-6); the oracle computes
+    the same lineage in FP64 from them and the device replays its draws:
+    fitness within 1e-4 at every generation."""
+    d = dataset(2500, 700, 3, seed=31)
+    m = r = 16
+    k = 16
+    G = 4
+    s = gsgp.Settings(pop_size=m, pool_size=r, genome_len=k, n_generations_max=G, seed=77,
+                      tournament_size=tsize, p_crossover=pxo, precision=precision)
+    cfg = oracle_config(s)
+    cp, vp = orc.genomes(cfg, 3, orc.TAG_POPULATION, m)
+    cr, vr = orc.genomes(cfg, 3, orc.TAG_POOL, r)
+    for i in range(12):
+        c = 1.5e-6 if i % 2 == 0 else -1.5e-6
+        cp[i] = [orc.GENE_CONST, 0] + [orc.GENE_CONST, orc.GENE_DIV] * 7
+        vp[i] = [0.25, 0.0] + [c, 0.0] * 7
+    codes, consts = np.concatenate([cp, cr]), np.concatenate([vp, vr])
+    Xtr, Xte, ytr, yte = d.X_train, d.X_test, d.y_train, d.y_test
+    S_tr, S_te = orc.interpret(cp, vp, Xtr), orc.interpret(cp, vp, Xte)
+    assert np.sum(np.abs(S_tr) == 3.4028234663852886e38) > 10000  # saturated cases present
+    sig_tr, sig_te = orc.sigmoid(orc.interpret(cr, vr, Xtr)), orc.sigmoid(orc.interpret(cr, vr, Xte))
+    F, Ft = orc.rmse_rows(S_tr, ytr), orc.rmse_rows(S_te, yte)
+    R = _runner(s, [d])
+    R.eval_population(codes, consts)
+    Fg, Ftg = R.fitness(0)
+    assert np.all(np.isfinite(Fg)) and np.max(Fg) > 1e37
+    assert rel_err(Fg, F, 1e-300) <= 1e-5 and rel_err(Ftg, Ft, 1e-300) <= 1e-5
+    for g in range(1, G + 1):
+        rec = orc.select(cfg, g, F)
+        O_tr, O_te = orc.vary(rec, S_tr, sig_tr), orc.vary(rec, S_te, sig_te)
+        F_O, Ft_O = orc.rmse_rows(O_tr, ytr), orc.rmse_rows(O_te, yte)
+        copied, src, dst = orc.survive(F, Ft, F_O, Ft_O, S_tr, O_tr, S_te, O_te)
+        grec = np.zeros((1, m), dtype=gsgp.RECORD_DTYPE)
+        for f in ("op", "p1", "p2", "r1", "r2", "ms"):
+            grec[0][f] = rec[f]
+        el = np.zeros(1, dtype=gsgp.STATS_DTYPE)
+        el["elite_copied"], el["elite_src"], el["elite_dst"] = copied, src, dst
+        R.replay(grec, el)
+        Fg, Ftg = R.fitness(0)
+        if tsize == 0 or g == 1:  # tournaments soon select the saturated rows away
+            assert np.max(Fg) > 1e37, g
+        assert rel_err(Fg, F_O, 1e-300) <= 1e-4, (g, rel_err(Fg, F_O, 1e-300))
+        assert rel_err(Ftg, Ft_O, 1e-300) <= 1e-4, g
+        S_tr, S_te, F, Ft = O_tr, O_te, F_O, Ft_O
+    R.close()
+
+
 def test_fp64_replay_of_oracle_lineage_matches():
     d = dataset(800, 200, 5, seed=2)
     G = 10
