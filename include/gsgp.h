@@ -252,7 +252,8 @@ gsgp_status gsgp_set_launch(gsgp_handle* h, int32_t waves_per_block, int32_t off
  * (the kernel is idempotent within a generation, so the runs do not
  * advance) and keeps the fastest.  h_best (HOST, nullable) receives
  * {waves_per_block, offspring_per_block, xcd_remap, max_blocks}.
- * Errors: GSGP_ERR_STATE, GSGP_ERR_HIP. */
+ * Errors: GSGP_ERR_STATE (also when no generation is left to run),
+ * GSGP_ERR_HIP. */
 gsgp_status gsgp_autotune(gsgp_handle* h, int32_t* h_best);
 
 /* Releases host resources.  The workspace stays the caller's. */

@@ -791,6 +791,9 @@ gsgp_status gsgp_autotune(gsgp_handle* h, int32_t* h_best) {
   gsgp_status st = usable(h);
   if (st != GSGP_OK) return st;
   if (!h->evaluated) return fail(GSGP_ERR_STATE, "gsgp_eval_population has not run");
+  // the trial launches read the next generation's records
+  if (h->gen >= h->cfg.n_generations_max)
+    return fail(GSGP_ERR_STATE, "no generation left to time (%d of %d done)", h->gen, h->cfg.n_generations_max);
   // The variation kernel is idempotent for a fixed generation (it reads the
   // parents and writes the offspring buffer), so shapes can be timed on the
   // live buffers without advancing the run.

@@ -333,6 +333,27 @@ def test_determinism_two_runs_identical():
     assert np.array_equal(outs[0][2], outs[1][2])
 
 
+def test_autotune_does_not_advance_or_change_the_run():
+    """Trial launches of the variation kernel at the current generation are
+    idempotent: a run tuned mid-way equals an untuned one bit for bit."""
+    d = dataset(3000, 500, 5, seed=8)
+    s = gsgp.Settings(pop_size=48, pool_size=32, n_generations_max=12, seed=5, precision=gsgp.FP32)
+    out = []
+    for tune in (False, True):
+        R = _runner(s, [d])
+        R.eval_population()
+        R.generation(4)
+        if tune:
+            best = R.autotune()
+            assert best["waves"] in (2, 4, 8) and R.current_generation() == 4
+        R.generation(8)
+        out.append((R.fitness(0), R.semantics(0, 0), R.stats(0, 0, 13)))
+        R.close()
+    (fa, sa, ta), (fb, sb, tb) = out
+    assert np.array_equal(fa[0], fb[0]) and np.array_equal(fa[1], fb[1])
+    assert np.array_equal(sa, sb) and np.array_equal(ta, tb)
+
+
 def test_error_paths():
     d = dataset(100, 20, 3)
     s = gsgp.Settings(pop_size=8, pool_size=4, n_generations_max=2, seed=1)
@@ -345,6 +366,9 @@ def test_error_paths():
         R.generation(3)
     assert e.value.status == -1
     R.generation(2)
+    with pytest.raises(gsgp.GSGPError) as e:
+        R.autotune()  # no generation left whose records a trial could read
+    assert e.value.status == -2
     with pytest.raises(gsgp.GSGPError):
         R.records(0, 3, 1)
     bad = np.zeros((12, 127), np.int32)
