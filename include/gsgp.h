@@ -194,6 +194,19 @@ gsgp_status gsgp_reconstruct(gsgp_handle* h, int32_t run, int32_t gen, int32_t i
                              const double* d_X, int64_t n, double* d_out, void* d_scratch,
                              size_t scratch_bytes);
 
+/* Compact model of a mutation-only lineage (the paper's own loop; GSM,
+ * Section 2, and the lineage structures of Section 2.1 stage 3): individual
+ * `individual` of generation `gen` of run `run` equals
+ * T(x) + sum_j w_j * sigmoid(R_j(x)), with T the generation-0 population tree
+ * *h_tree (HOST) and R_j the pool trees (genomes from gsgp_get_genomes).
+ * h_weights (HOST, r doubles) receives w, accumulated forward generation by
+ * generation (w[r1] += ms, then w[r2] -= ms).  Reads the ancestry record
+ * (synchronises the stream).
+ * Errors: GSGP_ERR_ARG, GSGP_ERR_STATE, GSGP_ERR_UNSUPPORTED (the lineage
+ * contains a crossover), GSGP_ERR_HIP. */
+gsgp_status gsgp_export_linear(gsgp_handle* h, int32_t run, int32_t gen, int32_t individual,
+                               int32_t* h_tree, double* h_weights);
+
 /* ---- inspection (HOST outputs; each synchronises the stream) ---------- */
 
 /* Current generation number (0 after gsgp_eval_population). */

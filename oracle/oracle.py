@@ -364,3 +364,33 @@ def reconstruct(res: Result, cfg: Config, gen: int, individual: int, X: np.ndarr
                 nxt[i] = vals[int(d["p1"])] + float(d["ms"]) * (sig[int(d["r1"])] - sig[int(d["r2"])])
         vals = nxt
     return vals[individual]
+
+
+def export_linear(res: Result, cfg: Config, gen: int, individual: int):
+    """Compact model of a mutation-only lineage (the paper's own loop).
+
+    Along a lineage of mutations only, individual ``individual`` of
+    generation ``gen`` is T(x) + sum_j w_j sigma(R_j(x)): one generation-0
+    population tree T and a weight per pool tree R_j, since every GSM step
+    adds ms (sigma(R_u) - sigma(R_v)) (Section 2, GSM; Section 2.1 stage 3,
+    lineage structures).  Returns (tree index, weights [r]); the weights are
+    accumulated forward, generation by generation (w[u] += ms, then
+    w[v] -= ms).  Raises ValueError if the lineage contains a crossover."""
+    m, r = cfg.pop_size, cfg.pool_size
+    muts = []
+    i = individual
+    for g in range(gen, 0, -1):
+        copied, src, dst = (int(v) for v in res.elite[g - 1])
+        if copied and i == dst:
+            i = src
+            continue
+        d = res.records[g - 1][i]
+        if d["op"] == OP_XO:
+            raise ValueError(f"the lineage contains a crossover at generation {g}")
+        muts.append(d)
+        i = int(d["p1"])
+    w = np.zeros(r)
+    for d in reversed(muts):
+        w[int(d["r1"])] += float(d["ms"])
+        w[int(d["r2"])] -= float(d["ms"])
+    return i, w

@@ -932,6 +932,47 @@ gsgp_status gsgp_reconstruct_scratch_size(gsgp_handle* h, int32_t run, int32_t g
   return GSGP_OK;
 }
 
+gsgp_status gsgp_export_linear(gsgp_handle* h, int32_t run, int32_t gen, int32_t individual, int32_t* h_tree,
+                               double* h_weights) {
+  gsgp_status st = check_run(h, run);
+  if (st != GSGP_OK) return st;
+  if (gen < 0 || gen > h->gen) return fail(GSGP_ERR_ARG, "generation %d not in [0, %d]", gen, h->gen);
+  if (individual < 0 || individual >= h->cfg.pop_size) return fail(GSGP_ERR_ARG, "individual out of range");
+  if (!h_tree || !h_weights) return fail(GSGP_ERR_ARG, "NULL output pointer");
+  const int32_t m = h->cfg.pop_size, r = h->cfg.pool_size;
+  const RunDev& R = h->runs_h[run];
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  std::vector<gsgp_record> rec((size_t)gen * m);
+  std::vector<gsgp_gen_stats> stats((size_t)gen + 1);
+  if (gen > 0) {
+    HIPCHK(h, hipMemcpy(rec.data(), R.rec, sizeof(gsgp_record) * gen * m, hipMemcpyDeviceToHost));
+    HIPCHK(h, hipMemcpy(stats.data(), R.stats, sizeof(gsgp_gen_stats) * (gen + 1), hipMemcpyDeviceToHost));
+  }
+  // walk back to the generation-0 tree, keeping the mutations in order
+  std::vector<const gsgp_record*> muts;
+  int32_t i = individual;
+  for (int32_t g = gen; g >= 1; --g) {
+    const gsgp_gen_stats& s = stats[g];
+    if (s.elite_copied && i == s.elite_dst) {
+      i = s.elite_src;
+      continue;
+    }
+    const gsgp_record& d = rec[(size_t)(g - 1) * m + i];
+    if (d.op == 1) return fail(GSGP_ERR_UNSUPPORTED, "the lineage contains a crossover at generation %d", g);
+    muts.push_back(&d);
+    i = d.p1;
+  }
+  // forward accumulation: w[r1] += ms, then w[r2] -= ms, generation by generation
+  std::vector<double> w(r, 0.0);
+  for (auto it = muts.rbegin(); it != muts.rend(); ++it) {
+    w[(*it)->r1] += (*it)->ms;
+    w[(*it)->r2] -= (*it)->ms;
+  }
+  *h_tree = i;
+  std::copy(w.begin(), w.end(), h_weights);
+  return GSGP_OK;
+}
+
 gsgp_status gsgp_reconstruct(gsgp_handle* h, int32_t run, int32_t gen, int32_t individual, const double* d_X,
                              int64_t n, double* d_out, void* d_scratch, size_t scratch_bytes) {
   gsgp_status st = check_run(h, run);

@@ -32,7 +32,7 @@ STATS_DTYPE = np.dtype([("best_train_rmse", "<f8"), ("best_test_rmse", "<f8"),
 # Every entry point declared in include/gsgp.h.
 EXPORTS = [
     "gsgp_workspace_size", "gsgp_init", "gsgp_eval_population", "gsgp_generation",
-    "gsgp_generation_replay", "gsgp_reconstruct_scratch_size", "gsgp_reconstruct",
+    "gsgp_generation_replay", "gsgp_reconstruct_scratch_size", "gsgp_reconstruct", "gsgp_export_linear",
     "gsgp_current_generation", "gsgp_get_fitness", "gsgp_get_semantics", "gsgp_get_records",
     "gsgp_get_stats", "gsgp_get_genomes", "gsgp_time_stages", "gsgp_time_eval", "gsgp_set_launch",
     "gsgp_autotune", "gsgp_destroy", "gsgp_status_string", "gsgp_last_error",
@@ -87,6 +87,7 @@ def lib():
             "gsgp_generation_replay": [P, I32, P, P, P],
             "gsgp_reconstruct_scratch_size": [P, I32, I32, I32, I64, P],
             "gsgp_reconstruct": [P, I32, I32, I32, P, I64, P, P, ctypes.c_size_t],
+            "gsgp_export_linear": [P, I32, I32, I32, P, P],
             "gsgp_current_generation": [P, P],
             "gsgp_get_fitness": [P, I32, P, P],
             "gsgp_get_semantics": [P, I32, I32, P],
@@ -304,6 +305,15 @@ class Runner:
         consts = np.zeros((rows, k))
         check(lib().gsgp_get_genomes(self._h, run, _ptr(codes), _ptr(consts)), "gsgp_get_genomes")
         return codes, consts
+
+    def export_linear(self, run: int, gen: int, individual: int):
+        """(tree, weights): individual = tree(x) + weights . sigmoid(pool(x))
+        for a mutation-only lineage; raises GSGPError (unsupported) otherwise."""
+        tree = ctypes.c_int32(0)
+        w = np.zeros(self.r)
+        check(lib().gsgp_export_linear(self._h, run, gen, individual, ctypes.byref(tree), _ptr(w)),
+              "gsgp_export_linear")
+        return int(tree.value), w
 
     def reconstruct(self, run: int, gen: int, individual: int, X: np.ndarray) -> np.ndarray:
         torch = self.torch

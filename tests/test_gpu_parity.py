@@ -318,6 +318,43 @@ def test_reconstruct_best_individual():
     R.close()
 
 
+def test_export_linear_equals_oracle_and_reconstruction():
+    """Paper loop (every individual mutated, random step): the device's
+    compact model of every individual equals the oracle's bit for bit (same
+    records, same accumulation order), and evaluating it reproduces the
+    device's own reconstruction on new cases; a crossover lineage is
+    rejected as unsupported."""
+    d = dataset(600, 150, 4, seed=15)
+    G = 16
+    s = gsgp.Settings(pop_size=24, pool_size=20, n_generations_max=G, seed=19, tournament_size=0,
+                      p_crossover=0.0, ms_random=1)
+    cfg = oracle_config(s)
+    res = orc.run(cfg, d.X_train, d.y_train, d.X_test, d.y_test, G)
+    R = _runner(s, [d])
+    R.eval_population()
+    R.generation(G)
+    codes, consts = R.genomes(0)
+    Xnew = np.random.default_rng(4).uniform(-1, 1, size=(77, 4))
+    sig = orc.sigmoid(orc.interpret(codes[s.pop_size:], consts[s.pop_size:], Xnew))
+    for i in range(s.pop_size):
+        tree, w = R.export_linear(0, G, i)
+        otree, ow = orc.export_linear(res, cfg, G, i)
+        assert tree == otree and np.array_equal(w, ow), i
+        val = orc.interpret(codes[tree:tree + 1], consts[tree:tree + 1], Xnew)[0] + w @ sig
+        rec = R.reconstruct(0, G, i, Xnew)
+        assert np.allclose(val, rec, rtol=1e-12, atol=1e-12 * np.max(np.abs(rec))), i
+    R.close()
+    s2 = gsgp.Settings(pop_size=24, pool_size=20, n_generations_max=4, seed=19)
+    R2 = _runner(s2, [d])
+    R2.eval_population()
+    R2.generation(4)
+    with pytest.raises(gsgp.GSGPError) as e:
+        for i in range(s2.pop_size):
+            R2.export_linear(0, 4, i)
+    assert e.value.status == -6
+    R2.close()
+
+
 def test_determinism_two_runs_identical():
     d = dataset(2500, 600, 6, seed=7)
     s = gsgp.Settings(pop_size=64, pool_size=64, n_generations_max=6, seed=31, precision=gsgp.FP32_KAHAN)

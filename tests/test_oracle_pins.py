@@ -526,3 +526,32 @@ def test_reconstruct_mutation_only_closed_form(orc):
             assert d["p1"] == i and d["op"] == orc.OP_MUT
             val += float(d["ms"]) * (sig[int(d["r1"])] - sig[int(d["r2"])])
         assert np.allclose(val, res.S_train[i], rtol=1e-12, atol=1e-12)
+
+
+def test_export_linear_evaluates_to_the_lineage(orc):
+    """The compact model of a mutation-only lineage, evaluated as
+    T(x) + sum_j w_j sigma(R_j(x)), equals the individual's semantics on the
+    training cases and on new cases (through reconstruction), elite copies
+    included; a lineage with a crossover has no such model."""
+    cfg = orc.Config(pop_size=8, pool_size=6, tournament_size=0, p_crossover=0.0, ms_random=1, seed=31)
+    Xtr, ytr, Xte, yte = _small_data(n_tr=20, n_te=6, seed=9)
+    G = 14
+    res = orc.run(cfg, Xtr, ytr, Xte, yte, G)
+    assert res.elite[:, 0].sum() > 0  # the walk crosses elite copies
+    m = cfg.pop_size
+    Xnew = np.random.default_rng(5).uniform(-1, 1, size=(9, Xtr.shape[1]))
+    for X, want_of in ((Xtr, lambda i: res.S_train[i]), (Xnew, lambda i: orc.reconstruct(res, cfg, G, i, Xnew))):
+        sig = orc.sigmoid(orc.interpret(res.code[m:], res.cval[m:], X))
+        for i in range(m):
+            tree, w = orc.export_linear(res, cfg, G, i)
+            val = orc.interpret(res.code[tree:tree + 1], res.cval[tree:tree + 1], X)[0] + w @ sig
+            want = want_of(i)
+            assert np.allclose(val, want, rtol=1e-12, atol=1e-12 * np.max(np.abs(want)))
+    # generation 0: the tree itself, no weights
+    tree, w = orc.export_linear(res, cfg, 0, 3)
+    assert tree == 3 and not w.any()
+    cfg2 = orc.Config(pop_size=8, pool_size=6, seed=31)  # tournaments and crossover
+    res2 = orc.run(cfg2, Xtr, ytr, Xte, yte, 6)
+    with pytest.raises(ValueError):
+        for i in range(8):
+            orc.export_linear(res2, cfg2, 6, i)
