@@ -327,6 +327,7 @@ def bench_batched(args) -> dict:
 
     B = gsgp.Runner(settings_for(gsgp, wl, G, gsgp.FP32_KAHAN, seed), datasets, stream=stream)
     B.eval_population()
+    tuned = None if args.no_autotune else B.autotune()
     B.generation(min(G, 3), stats=False)  # warm up graph capture
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -338,7 +339,20 @@ def bench_batched(args) -> dict:
     elite = np.stack([B.stats(j, 1, G) for j in range(n_runs)])
     final = np.stack([B.stats(j, G, 1)[0] for j in range(n_runs)])
     F_b = np.stack([B.fitness(j)[0] for j in range(n_runs)])
+    # roofline of the batched variation launch: algorithmic bytes of every
+    # run (distinct parent / pool rows from its records) over the launch time
+    B.eval_population()
+    ng = min(G, 20)
+    stg = B.time_stages(ng)
+    chunk = 4096 // 4
+    alg = 0.0
+    for j, d in enumerate(datasets):
+        n_tr, n_te = d.X_train.shape[0], d.X_test.shape[0]
+        n_chunks = -(-(-(-n_tr // 64) * 64) // chunk) + -(-(-(-n_te // 64) * 64) // chunk)
+        rj = B.records(j, 1, ng)
+        alg += float(np.mean([vary_bytes(rj[g], n_tr + n_te, 4, wl.pop_size, n_chunks) for g in range(ng)]))
     B.close()
+    achieved = alg / (stg["vary_ms"] * 1e-3) / 1e9
 
     R64 = gsgp.Runner(settings_for(gsgp, wl, G, gsgp.FP64, seed), datasets, stream=stream)
     R64.eval_population()
@@ -367,7 +381,11 @@ def bench_batched(args) -> dict:
     return {"metric": "runs/hour, batched FP32-Kahan vs plain per-run", "value": n_runs * 3600 / t_batched,
             "unit": "runs/hour", "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
             "config": {"workload": wl.name, "runs": n_runs, "total_cases": n_all, "pop_size": wl.pop_size,
-                       "pool_size": wl.pool_size, "generations": G},
+                       "pool_size": wl.pool_size, "generations": G, "launch": tuned},
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "kernel": "k_vary over all runs (one launch)",
+                         "alg_bytes_per_launch": alg, "launch_ms": stg["vary_ms"]},
+            "stages_ms": {k: round(v, 5) for k, v in stg.items()},
             "batched_fp32_kahan_graph": {"runs_per_hour": n_runs * 3600 / t_batched, "seconds": t_batched,
                                          "offspring_elements_per_s": wl.pop_size * n_all * G / t_batched},
             "plain_per_run_fp64": {"runs_per_hour": n_runs * 3600 / t_plain, "seconds": t_plain},
