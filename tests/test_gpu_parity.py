@@ -112,6 +112,28 @@ def test_ragged_and_edge_sizes(n_train, n_test, l):
     _free_run_parity(s, d, 6)
 
 
+@pytest.mark.parametrize("variant", ["population_beyond_lds", "genomes_2047", "tournament_64",
+                                     "single_individual"])
+def test_extreme_sizes(variant):
+    """Limits of the launch plans: a population above the survival kernel's
+    LDS staging limit (4,096), the paper's longest programs (k = 2,047), the
+    largest tournament (64 candidates) and a population of one."""
+    G = 3
+    if variant == "population_beyond_lds":
+        d = dataset(200, 50, 3, seed=21)
+        s = gsgp.Settings(pop_size=4160, pool_size=64, n_generations_max=G, seed=13)
+    elif variant == "genomes_2047":
+        d = dataset(300, 100, 5, seed=22)
+        s = gsgp.Settings(pop_size=16, pool_size=8, genome_len=2047, n_generations_max=G, seed=14)
+    elif variant == "tournament_64":
+        d = dataset(300, 100, 4, seed=23)
+        s = gsgp.Settings(pop_size=80, pool_size=16, tournament_size=64, n_generations_max=G, seed=15)
+    else:
+        d = dataset(300, 100, 4, seed=24)
+        s = gsgp.Settings(pop_size=1, pool_size=3, n_generations_max=G, seed=16)
+    _free_run_parity(s, d, G)
+
+
 @pytest.mark.parametrize("variant", ["paper_mutate_all", "ms_random", "all_crossover", "pool_one",
                                      "tournament_one", "short_genomes"])
 def test_operator_variants(variant):
