@@ -220,6 +220,12 @@ gsgp_status gsgp_get_fitness(gsgp_handle* h, int32_t run, double* h_train, doubl
  * [r][n_train + n_test]; train cases then test cases in each row. */
 gsgp_status gsgp_get_semantics(gsgp_handle* h, int32_t run, int32_t which, double* h_out);
 
+/* Rows row0 .. row0 + n_rows - 1 of the same (h_out: [n_rows][n_train +
+ * n_test] FP64), copying only those rows from the device: for inspecting a
+ * few individuals of a large run. */
+gsgp_status gsgp_get_semantics_rows(gsgp_handle* h, int32_t run, int32_t which, int32_t row0, int32_t n_rows,
+                                    double* h_out);
+
 /* Variation records of generations gen0 .. gen0 + n_gens - 1 (1-based,
  * <= current), [n_gens][m].  raw = 1 returns the draws as made; raw = 0
  * returns the lineage view, where the offspring replaced by an elite copy

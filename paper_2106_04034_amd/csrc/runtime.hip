@@ -651,23 +651,37 @@ gsgp_status gsgp_get_fitness(gsgp_handle* h, int32_t run, double* h_train, doubl
   return GSGP_OK;
 }
 
-gsgp_status gsgp_get_semantics(gsgp_handle* h, int32_t run, int32_t which, double* h_out) {
+gsgp_status gsgp_get_semantics_rows(gsgp_handle* h, int32_t run, int32_t which, int32_t row0, int32_t n_rows,
+                                    double* h_out) {
   gsgp_status st = check_run(h, run);
   if (st != GSGP_OK) return st;
   if (which != 0 && which != 1) return fail(GSGP_ERR_ARG, "which must be 0 (population) or 1 (pool)");
   if (!h_out) return fail(GSGP_ERR_ARG, "h_out is NULL");
+  const int64_t rows = which == 0 ? h->cfg.pop_size : h->cfg.pool_size;
+  if (row0 < 0 || n_rows < 1 || (int64_t)row0 + n_rows > rows)
+    return fail(GSGP_ERR_ARG, "rows %d..%d not in [0, %lld)", row0, row0 + n_rows - 1, (long long)rows);
   HIPCHK(h, hipStreamSynchronize(h->stream));
   const RunDev& R = h->runs_h[run];
-  const int64_t rows = which == 0 ? h->cfg.pop_size : h->cfg.pool_size;
   const size_t s = storage_bytes(h->cfg.precision);
-  std::vector<char> raw((size_t)rows * R.ld * s);
-  const void* from = which == 0 ? R.S[h->gen & 1] : R.sigR;
-  HIPCHK(h, hipMemcpy(raw.data(), from, raw.size(), hipMemcpyDeviceToHost));
+  const int64_t CH = chunk_cases((int)s);
+  // gather the rows' part of every chunk block into a tiled buffer of n_rows rows
+  std::vector<char> raw((size_t)n_rows * R.ld * s);
+  const char* from = (const char*)(which == 0 ? R.S[h->gen & 1] : R.sigR);
+  for (int32_t c = 0; c < R.nch; ++c) {
+    const ChunkGeom g = chunk_geom(R.tr_pad, R.te_pad, R.nch_tr, c, CH);
+    HIPCHK(h, hipMemcpy(raw.data() + (size_t)n_rows * g.cs * s, from + (size_t)(rows * g.cs + row0 * g.len) * s,
+                        (size_t)n_rows * g.len * s, hipMemcpyDeviceToHost));
+  }
   if (s == 8)
-    to_f64<double>(raw, rows, R, h_out);
+    to_f64<double>(raw, n_rows, R, h_out);
   else
-    to_f64<float>(raw, rows, R, h_out);
+    to_f64<float>(raw, n_rows, R, h_out);
   return GSGP_OK;
+}
+
+gsgp_status gsgp_get_semantics(gsgp_handle* h, int32_t run, int32_t which, double* h_out) {
+  if (which != 0 && which != 1) return fail(GSGP_ERR_ARG, "which must be 0 (population) or 1 (pool)");
+  return gsgp_get_semantics_rows(h, run, which, 0, which == 0 ? h->cfg.pop_size : h->cfg.pool_size, h_out);
 }
 
 gsgp_status gsgp_get_records(gsgp_handle* h, int32_t run, int32_t gen0, int32_t n_gens, int32_t raw,

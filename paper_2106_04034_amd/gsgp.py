@@ -33,7 +33,8 @@ STATS_DTYPE = np.dtype([("best_train_rmse", "<f8"), ("best_test_rmse", "<f8"),
 EXPORTS = [
     "gsgp_workspace_size", "gsgp_init", "gsgp_eval_population", "gsgp_generation",
     "gsgp_generation_replay", "gsgp_reconstruct_scratch_size", "gsgp_reconstruct", "gsgp_export_linear",
-    "gsgp_current_generation", "gsgp_get_fitness", "gsgp_get_semantics", "gsgp_get_records",
+    "gsgp_current_generation", "gsgp_get_fitness", "gsgp_get_semantics", "gsgp_get_semantics_rows",
+    "gsgp_get_records",
     "gsgp_get_stats", "gsgp_get_genomes", "gsgp_time_stages", "gsgp_time_eval", "gsgp_set_launch",
     "gsgp_autotune", "gsgp_destroy", "gsgp_status_string", "gsgp_last_error",
 ]
@@ -91,6 +92,7 @@ def lib():
             "gsgp_current_generation": [P, P],
             "gsgp_get_fitness": [P, I32, P, P],
             "gsgp_get_semantics": [P, I32, I32, P],
+            "gsgp_get_semantics_rows": [P, I32, I32, I32, I32, P],
             "gsgp_get_records": [P, I32, I32, I32, I32, P],
             "gsgp_get_stats": [P, I32, I32, I32, P],
             "gsgp_get_genomes": [P, I32, P, P],
@@ -280,6 +282,13 @@ class Runner:
         te = np.zeros(self.m)
         check(lib().gsgp_get_fitness(self._h, run, _ptr(tr), _ptr(te)), "gsgp_get_fitness")
         return tr, te
+
+    def semantics_rows(self, run: int, which: int, row0: int, n_rows: int) -> np.ndarray:
+        n_tr, n_te, _ = self.shapes[run]
+        out = np.zeros((n_rows, n_tr + n_te))
+        check(lib().gsgp_get_semantics_rows(self._h, run, which, row0, n_rows, _ptr(out)),
+              "gsgp_get_semantics_rows")
+        return out
 
     def semantics(self, run: int = 0, which: int = 0) -> np.ndarray:
         n_tr, n_te, _ = self.shapes[run]
