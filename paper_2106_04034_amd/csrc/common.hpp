@@ -143,8 +143,8 @@ hipError_t launch_set_state(const RunDev* d_runs, int32_t n_runs, int32_t word, 
 hipError_t launch_genome(const RunDev* d_runs, const Params& p, hipStream_t s);
 hipError_t launch_compile(const RunDev* d_runs, const Params& p, hipStream_t s);
 // slots: stack values per lane kept in LDS (deepest stack - 2, at least 1).
-hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_blocks, int max_features,
-                            int slots, hipStream_t s);
+hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_blocks, int slots,
+                            hipStream_t s);
 hipError_t launch_vary(const RunDev* d_runs, const Params& p, const VaryLaunch& lc, bool rows_only,
                        hipStream_t s);
 hipError_t launch_fitness(const RunDev* d_runs, const Params& p, bool init, hipStream_t s);

@@ -259,9 +259,10 @@ __global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs
 // from LDS only after it has produced its result, so the LDS latency falls
 // outside the op's dependency chain.  The value of the program is the
 // output of its last function (the Out register), 0.0 if none runs.
-// X is the feature-major case block: in LDS (XLDS, ld = cases per block) or
-// in global memory (lanes whose column is out of range read nothing).
-template <int V, bool XLDS>
+// X is feature-major in global memory, row stride ld (lanes whose column is
+// out of range read nothing); one case block's features stay in L2 while
+// the block's programs run.
+template <int V>
 __device__ __forceinline__ void eval_program(const int32_t* ops, const double* opv, int n, const double* X,
                                              int64_t ld, const int64_t (&col)[V], const bool (&ok)[V],
                                              double* stk_lds, int lane, double (&out)[V]) {
@@ -299,15 +300,9 @@ __device__ __forceinline__ void eval_program(const int32_t* ops, const double* o
         for (int v = 0; v < V; ++v) nos[v] = tos[v];
         if (kind == kPushFeature) {
           const int f = (int)((uint32_t)w >> 16);
-          if constexpr (XLDS) {
-            const GSGP_LDS double* xl = (const GSGP_LDS double*)X + f * (int)ld;
+          const GSGP_GLOBAL double* xg = (const GSGP_GLOBAL double*)X + (int64_t)f * ld;
 #pragma unroll
-            for (int v = 0; v < V; ++v) tos[v] = xl[(int)col[v]];
-          } else {
-            const GSGP_GLOBAL double* xg = (const GSGP_GLOBAL double*)X + (int64_t)f * ld;
-#pragma unroll
-            for (int v = 0; v < V; ++v) tos[v] = ok[v] ? xg[col[v]] : 0.0;
-          }
+          for (int v = 0; v < V; ++v) tos[v] = ok[v] ? xg[col[v]] : 0.0;
         } else {
 #pragma unroll
           for (int v = 0; v < V; ++v) tos[v] = cv[u];
@@ -348,14 +343,15 @@ constexpr int kInterpTile = kWave * kInterpV;  // cases per block
 constexpr int kInterpProgsPerWave = 4;   // programs each wave interprets on its case block
 
 // ComputeSemantics(P) and ComputeSemantics(R) (Algorithm 1).  A block takes
-// one block of 128 cases of one run and a group of programs; with XLDS the
-// block first stages the cases' features in LDS so feature pushes read LDS,
-// then each wave interprets kInterpProgsPerWave programs.  Pool rows are
-// squashed by the logistic function (the random functions R_u of GSM,
+// one block of 128 cases of one run and a group of programs; each wave
+// interprets kInterpProgsPerWave programs on the block's cases.  Pool rows
+// are squashed by the logistic function (the random functions R_u of GSM,
 // Section 2) before storage.  Padding columns are written as exact zeros.
-template <typename T, bool XLDS>
+// (Staging the case block's features in LDS was slower: the tile cut the
+// number of resident waves more than it saved in L2 reads.)
+template <typename T>
 __global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ runs, Params p, int32_t pgroups,
-                                                   int slots, int32_t xtile_doubles) {
+                                                   int slots) {
   extern __shared__ double lds[];
   const int lane = threadIdx.x & 63;
   const int wave = uni(threadIdx.x >> 6);
@@ -367,33 +363,20 @@ __global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ ru
   const int64_t cb = cbg - R.cblk0;
   const int64_t ld = R.ld;
   const int rows = p.m + p.r;
-  double* stk = lds + xtile_doubles + wave * slots * kInterpV * kWave;
-  if constexpr (XLDS) {
-    for (int idx = threadIdx.x; idx < R.l * kInterpTile; idx += blockDim.x) {
-      const int f = idx / kInterpTile;
-      const int64_t gc = cb * kInterpTile + (idx - f * kInterpTile);
-      lds[idx] = gc < ld ? ((const GSGP_GLOBAL double*)R.X)[(int64_t)f * ld + gc] : 0.0;
-    }
-    __syncthreads();
-  }
-  int64_t col[kInterpV], xcol[kInterpV];
+  double* stk = lds + wave * slots * kInterpV * kWave;
+  int64_t col[kInterpV];
   bool ok[kInterpV];
 #pragma unroll
   for (int v = 0; v < kInterpV; ++v) {
     col[v] = cb * kInterpTile + v * kWave + lane;
     ok[v] = col[v] < ld;
-    xcol[v] = XLDS ? (int64_t)(v * kWave + lane) : col[v];
   }
   for (int j = 0; j < kInterpProgsPerWave; ++j) {
     const int prog = (pg * kInterpProgsPerWave + j) * W + wave;
     if (prog >= rows) break;
     double out[kInterpV];
-    if constexpr (XLDS)
-      eval_program<kInterpV, true>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k,
-                                   uni(cload(&R.nops[prog])), lds, kInterpTile, xcol, ok, stk, lane, out);
-    else
-      eval_program<kInterpV, false>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k,
-                                    uni(cload(&R.nops[prog])), R.X, ld, xcol, ok, stk, lane, out);
+    eval_program<kInterpV>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k, uni(cload(&R.nops[prog])),
+                           R.X, ld, col, ok, stk, lane, out);
     const bool pool = prog >= p.m;
     T* dst = pool ? (T*)R.sigR : (T*)R.S[0];
     const int64_t nrows = pool ? p.r : p.m;
@@ -1046,8 +1029,8 @@ __global__ __launch_bounds__(256) void k_interpret_list(const int32_t* __restric
   }
   double val[kInterpV];
   double* stk = lds + wave * slots * kInterpV * kWave;
-  eval_program<kInterpV, false>(ops + (int64_t)pr * k, opv + (int64_t)pr * k, uni(nops[pr]), Xfm, ld, col, ok,
-                                stk, lane, val);  // column index doubles as the X offset here
+  eval_program<kInterpV>(ops + (int64_t)pr * k, opv + (int64_t)pr * k, uni(nops[pr]), Xfm, ld, col, ok, stk, lane,
+                         val);
   const bool sq = squash[j] != 0;
 #pragma unroll
   for (int v = 0; v < kInterpV; ++v) {
@@ -1129,36 +1112,19 @@ hipError_t launch_compile(const RunDev* d_runs, const Params& p, hipStream_t s) 
   return hipGetLastError();
 }
 
-hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_blocks, int max_features,
-                            int slots, hipStream_t s) {
+hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_blocks, int slots,
+                            hipStream_t s) {
   if (slots < 1) slots = 1;
-  // LDS budget 64 KiB: the features of 128 cases (when staged) plus one
-  // stack column block per wave.
-  const int64_t stack_per_wave = (int64_t)slots * kInterpV * kWave * sizeof(double);
-  const int64_t xtile = (int64_t)max_features * kInterpTile * sizeof(double);
-  int waves = 4;
-  bool xlds = true;
-  while (waves > 1 && xtile + waves * stack_per_wave > 65536) --waves;
-  if (xtile + waves * stack_per_wave > 65536) {
-    xlds = false;
-    waves = interp_waves(slots);
-  }
+  // one LDS stack column block per wave, at most 64 KiB per block
+  const int waves = interp_waves(slots);
+  const size_t shmem = (size_t)waves * slots * kInterpV * kWave * sizeof(double);
   const int rows = p.m + p.r;
   const int32_t pgroups = (rows + waves * kInterpProgsPerWave - 1) / (waves * kInterpProgsPerWave);
-  const int32_t xdoubles = xlds ? (int32_t)(xtile / sizeof(double)) : 0;
-  const size_t shmem = (size_t)xdoubles * sizeof(double) + (size_t)waves * stack_per_wave;
   const dim3 grid((unsigned)(case_blocks * pgroups)), block(waves * kWave);
-  if (p.precision == GSGP_FP64) {
-    if (xlds)
-      hipLaunchKernelGGL((k_interpret<double, true>), grid, block, shmem, s, d_runs, p, pgroups, slots, xdoubles);
-    else
-      hipLaunchKernelGGL((k_interpret<double, false>), grid, block, shmem, s, d_runs, p, pgroups, slots, xdoubles);
-  } else {
-    if (xlds)
-      hipLaunchKernelGGL((k_interpret<float, true>), grid, block, shmem, s, d_runs, p, pgroups, slots, xdoubles);
-    else
-      hipLaunchKernelGGL((k_interpret<float, false>), grid, block, shmem, s, d_runs, p, pgroups, slots, xdoubles);
-  }
+  if (p.precision == GSGP_FP64)
+    hipLaunchKernelGGL((k_interpret<double>), grid, block, shmem, s, d_runs, p, pgroups, slots);
+  else
+    hipLaunchKernelGGL((k_interpret<float>), grid, block, shmem, s, d_runs, p, pgroups, slots);
   return hipGetLastError();
 }
 

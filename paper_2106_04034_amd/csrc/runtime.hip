@@ -163,7 +163,6 @@ struct gsgp_handle {
   Params params;
   VaryLaunch vary{}, rows{};
   int64_t interp_tasks = 0;  // 128-case blocks over all runs
-  int32_t max_features = 0;
   int32_t surv_blocks = 0;
   int32_t slots = 1;         // interpreter stack values per lane in LDS
   int32_t max_blocks = 0;
@@ -425,7 +424,6 @@ gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_ru
     col += q.ld;
     R.cblk0 = itask;
     itask += (q.ld + 127) / 128;
-    h->max_features = std::max(h->max_features, q.l);
     R.surv_blk0 = sblk;
     // survival blocks per run: each copies about 16 KiB of an elite row
     const int64_t nb = ((int64_t)storage_bytes(cfg->precision) * q.ld + 16383) / 16384;
@@ -523,7 +521,7 @@ gsgp_status eval_impl(gsgp_handle* h, const int32_t* h_codes, const double* h_co
     return fail(GSGP_ERR_UNSUPPORTED, "a genome needs a stack of %d values; at most %d are supported", deepest, kMaxStack);
   }
   h->slots = std::max(1, deepest - 2);  // the top two values live in registers
-  HIPCHK(h, launch_interpret(h->runs_d, p, h->interp_tasks, h->max_features, h->slots, h->stream));
+  HIPCHK(h, launch_interpret(h->runs_d, p, h->interp_tasks, h->slots, h->stream));
   if (ev) HIPCHK(h, hipEventRecord(ev[2], h->stream));
   HIPCHK(h, launch_vary(h->runs_d, p, h->rows, true, h->stream));
   HIPCHK(h, launch_fitness(h->runs_d, p, true, h->stream));
