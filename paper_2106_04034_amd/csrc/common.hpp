@@ -22,6 +22,8 @@ constexpr int chunk_cases(int storage_bytes) { return kChunkBytes / storage_byte
 // multiple of this many cases; rows therefore start 256-byte aligned.
 constexpr int kSegPad = 64;
 constexpr int kWave = 64;
+// Interpreter work unit: a block of kInterpCases cases (kWave lanes x 2 cases).
+constexpr int kInterpCases = 128;
 constexpr int kMaxTournament = 64;
 // Deepest stack (values, top included) a compiled genome may need: the
 // interpreter keeps the top two values in registers and depth - 2 per lane

@@ -340,7 +340,8 @@ __device__ __forceinline__ void eval_program(const int32_t* ops, const double* o
 
 constexpr int kInterpV = 2;              // cases per lane
 constexpr int kInterpTile = kWave * kInterpV;  // cases per block
-constexpr int kInterpProgsPerWave = 4;   // programs each wave interprets on its case block
+static_assert(kInterpTile == kInterpCases, "the runtime plans kInterpCases-case blocks");
+constexpr int kInterpProgsPerWave = 8;   // programs each wave interprets on its case block
 
 // ComputeSemantics(P) and ComputeSemantics(R) (Algorithm 1).  A block takes
 // one block of 128 cases of one run and a group of programs; each wave

@@ -162,7 +162,7 @@ struct gsgp_handle {
   RunDev* runs_d = nullptr;
   Params params;
   VaryLaunch vary{}, rows{};
-  int64_t interp_tasks = 0;  // 128-case blocks over all runs
+  int64_t interp_tasks = 0;  // interpreter case blocks over all runs
   int32_t surv_blocks = 0;
   int32_t slots = 1;         // interpreter stack values per lane in LDS
   int32_t max_blocks = 0;
@@ -423,7 +423,7 @@ gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_ru
     R.col0 = col;
     col += q.ld;
     R.cblk0 = itask;
-    itask += (q.ld + 127) / 128;
+    itask += (q.ld + kInterpCases - 1) / kInterpCases;
     R.surv_blk0 = sblk;
     // survival blocks per run: each copies about 16 KiB of an elite row
     const int64_t nb = ((int64_t)storage_bytes(cfg->precision) * q.ld + 16383) / 16384;
