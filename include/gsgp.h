@@ -61,6 +61,10 @@ typedef enum { GSGP_FP64 = 0, GSGP_FP32 = 1, GSGP_FP32_KAHAN = 2 } gsgp_precisio
 
 /* gsgp_config.flags */
 #define GSGP_FLAG_NO_GRAPH 1u  /* launch generations one by one, no HIP graph */
+#define GSGP_FLAG_GUARDS 2u    /* debug: a 256-byte guard pattern after every workspace
+                                  buffer (gsgp_workspace_size grows accordingly), checked
+                                  after every call that launches kernels; an overwritten
+                                  guard poisons the handle (GSGP_ERR_STATE) */
 
 /* Run parameters: the inputs of Algorithm 1 plus operator settings.
  * Defaults used by the project's workloads are given in brackets. */
@@ -274,6 +278,12 @@ gsgp_status gsgp_set_launch(gsgp_handle* h, int32_t waves_per_block, int32_t off
  * Errors: GSGP_ERR_STATE (also when no generation is left to run),
  * GSGP_ERR_HIP. */
 gsgp_status gsgp_autotune(gsgp_handle* h, int32_t* h_best);
+
+/* Byte offsets (within the workspace) of the guards that GSGP_FLAG_GUARDS
+ * places after every buffer: *n receives their number, h_offsets (HOST,
+ * nullable when max = 0) the first min(max, *n) offsets.  For diagnostics
+ * and tests of the guard check itself.  Errors: GSGP_ERR_ARG. */
+gsgp_status gsgp_guard_offsets(gsgp_handle* h, int64_t* h_offsets, int32_t max, int32_t* n);
 
 /* Releases host resources.  The workspace stays the caller's. */
 gsgp_status gsgp_destroy(gsgp_handle* h);

@@ -55,9 +55,21 @@ struct RunPlan {
   size_t end;
 };
 
+// With GSGP_FLAG_GUARDS every buffer is followed by kGuardBytes of a fixed
+// pattern, checked after every call that launches kernels.
+constexpr size_t kGuardBytes = 256;
+constexpr uint32_t kGuardWord = 0xC0FFEE5Au;
+
+struct Guard {
+  size_t at;         // byte offset of the guard in the workspace
+  int32_t run;       // -1 for the shared buffers
+  const char* after; // the buffer it follows
+};
+
 struct Plan {
   size_t runs_dev, src_ptrs, state, total;
   std::vector<RunPlan> runs;
+  std::vector<Guard> guards;
 };
 
 gsgp_status validate_config(const gsgp_config* c) {
@@ -81,7 +93,7 @@ gsgp_status validate_config(const gsgp_config* c) {
       std::fabs(c->erc_lo) > 3.0e38 || std::fabs(c->erc_hi) > 3.0e38)
     return fail(GSGP_ERR_ARG, "constant range must be finite with erc_lo <= erc_hi");
   if (c->precision < GSGP_FP64 || c->precision > GSGP_FP32_KAHAN) return fail(GSGP_ERR_ARG, "unknown precision %d", c->precision);
-  if ((c->flags & ~GSGP_FLAG_NO_GRAPH) != 0) return fail(GSGP_ERR_ARG, "unknown flags 0x%x", c->flags);
+  if ((c->flags & ~(GSGP_FLAG_NO_GRAPH | GSGP_FLAG_GUARDS)) != 0) return fail(GSGP_ERR_ARG, "unknown flags 0x%x", c->flags);
   if (c->reserved != 0) return fail(GSGP_ERR_ARG, "reserved config field must be 0");
   return GSGP_OK;
 }
@@ -92,13 +104,22 @@ gsgp_status make_plan(const gsgp_config* c, const gsgp_run* runs, int32_t n_runs
   if (!runs || n_runs < 1 || n_runs > 65536) return fail(GSGP_ERR_ARG, "need 1..65536 runs");
   const int64_t m = c->pop_size, r = c->pool_size, k = c->genome_len, G = c->n_generations_max;
   const size_t s = storage_bytes(c->precision);
+  const bool guarded = (c->flags & GSGP_FLAG_GUARDS) != 0;
+  plan->guards.clear();
   size_t off = 0;
-  plan->runs_dev = off;
-  off = align_up(off + sizeof(RunDev) * n_runs);
-  plan->src_ptrs = off;
-  off = align_up(off + sizeof(double*) * 4 * n_runs);
-  plan->state = off;
-  off = align_up(off + sizeof(int32_t) * kStWords * n_runs);
+  // reserves `bytes` at the next aligned offset, plus a guard when asked
+  auto take_at = [&](size_t bytes, int32_t run, const char* name) {
+    const size_t at = off;
+    if (guarded) {
+      plan->guards.push_back(Guard{at + bytes, run, name});
+      bytes += kGuardBytes;
+    }
+    off = align_up(off + bytes);
+    return at;
+  };
+  plan->runs_dev = take_at(sizeof(RunDev) * n_runs, -1, "run descriptors");
+  plan->src_ptrs = take_at(sizeof(double*) * 4 * n_runs, -1, "input pointers");
+  plan->state = take_at(sizeof(int32_t) * kStWords * n_runs, -1, "state words");
   plan->runs.resize(n_runs);
   for (int32_t i = 0; i < n_runs; ++i) {
     const gsgp_run& d = runs[i];
@@ -120,29 +141,24 @@ gsgp_status make_plan(const gsgp_config* c, const gsgp_run* runs, int32_t n_runs
     const int64_t chunk = chunk_cases((int)s);
     p.nch_tr = (int32_t)((p.tr_pad + chunk - 1) / chunk);
     p.nch_te = (int32_t)((p.te_pad + chunk - 1) / chunk);
-    auto take = [&](size_t bytes) {
-      const size_t at = off;
-      off = align_up(off + bytes);
-      return at;
-    };
-    p.X = take(sizeof(double) * p.l * p.ld);
-    p.y = take(s * p.ld);
-    p.S0 = take(s * m * p.ld);
-    p.S1 = take(s * m * p.ld);
-    p.sigR = take(s * r * p.ld);
-    p.part = take(sizeof(double) * (p.nch_tr + p.nch_te) * m);
-    p.F0 = take(8 * m);
-    p.F1 = take(8 * m);
-    p.Ft0 = take(8 * m);
-    p.Ft1 = take(8 * m);
-    p.rec = take(sizeof(gsgp_record) * G * m);
-    p.stats = take(sizeof(gsgp_gen_stats) * (G + 1));
-    p.elite_in = take(sizeof(gsgp_gen_stats) * G);
-    p.code = take(4 * (m + r) * k);
-    p.cval = take(8 * (m + r) * k);
-    p.ops = take(4 * (m + r) * k);
-    p.opv = take(8 * (m + r) * k);
-    p.nops = take(4 * (m + r));
+    p.X = take_at(sizeof(double) * p.l * p.ld, i, "X");
+    p.y = take_at(s * p.ld, i, "y");
+    p.S0 = take_at(s * m * p.ld, i, "S[0]");
+    p.S1 = take_at(s * m * p.ld, i, "S[1]");
+    p.sigR = take_at(s * r * p.ld, i, "sigmoid(S_R)");
+    p.part = take_at(sizeof(double) * (p.nch_tr + p.nch_te) * m, i, "chunk partial sums");
+    p.F0 = take_at(8 * m, i, "F[0]");
+    p.F1 = take_at(8 * m, i, "F[1]");
+    p.Ft0 = take_at(8 * m, i, "Ft[0]");
+    p.Ft1 = take_at(8 * m, i, "Ft[1]");
+    p.rec = take_at(sizeof(gsgp_record) * G * m, i, "variation records");
+    p.stats = take_at(sizeof(gsgp_gen_stats) * (G + 1), i, "summaries");
+    p.elite_in = take_at(sizeof(gsgp_gen_stats) * G, i, "supplied survival decisions");
+    p.code = take_at(4 * (m + r) * k, i, "genome codes");
+    p.cval = take_at(8 * (m + r) * k, i, "genome constants");
+    p.ops = take_at(4 * (m + r) * k, i, "compiled ops");
+    p.opv = take_at(8 * (m + r) * k, i, "compiled constants");
+    p.nops = take_at(4 * (m + r), i, "program lengths");
     p.end = off;
   }
   plan->total = off;
@@ -190,7 +206,34 @@ gsgp_status hip_fail(gsgp_handle* h, hipError_t e, const char* what) {
 
 gsgp_status usable(gsgp_handle* h) {
   if (!h) return fail(GSGP_ERR_ARG, "handle is NULL");
-  if (h->poisoned) return fail(GSGP_ERR_STATE, "handle is poisoned by an earlier HIP error");
+  if (h->poisoned) return fail(GSGP_ERR_STATE, "handle is poisoned by an earlier error");
+  return GSGP_OK;
+}
+
+// Writes the guard pattern after every buffer (GSGP_FLAG_GUARDS).
+gsgp_status arm_guards(gsgp_handle* h) {
+  std::vector<uint32_t> pat(kGuardBytes / 4, kGuardWord);
+  for (const Guard& g : h->plan.guards)
+    HIPCHK(h, hipMemcpy(h->ws + g.at, pat.data(), kGuardBytes, hipMemcpyHostToDevice));
+  return GSGP_OK;
+}
+
+// After a call that launched kernels: `st` unless a guard was overwritten,
+// which poisons the handle and names the buffer it follows.
+gsgp_status check_guards(gsgp_handle* h, gsgp_status st) {
+  if (st != GSGP_OK || h->plan.guards.empty()) return st;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  std::vector<uint32_t> got(kGuardBytes / 4);
+  for (const Guard& g : h->plan.guards) {
+    HIPCHK(h, hipMemcpy(got.data(), h->ws + g.at, kGuardBytes, hipMemcpyDeviceToHost));
+    for (uint32_t w : got) {
+      if (w != kGuardWord) {
+        h->poisoned = true;
+        if (g.run < 0) return fail(GSGP_ERR_STATE, "workspace guard after the %s was overwritten", g.after);
+        return fail(GSGP_ERR_STATE, "workspace guard after %s of run %d was overwritten", g.after, g.run);
+      }
+    }
+  }
   return GSGP_OK;
 }
 
@@ -444,6 +487,11 @@ gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_ru
   }
   const double* const* d_src = (const double* const*)(ws + plan.src_ptrs);
   std::vector<int32_t> zeros((size_t)kStWords * n_runs, 0);
+  if (!h->plan.guards.empty() && arm_guards(h) != GSGP_OK) {
+    gsgp_status s2 = fail(GSGP_ERR_HIP, "gsgp_init: writing the workspace guards");
+    gsgp_destroy(h);
+    return s2;
+  }
   e = upload_runs(h);
   if (e == hipSuccess)
     e = hipMemcpyAsync((void*)d_src, src.data(), sizeof(double*) * src.size(), hipMemcpyHostToDevice, h->stream);
@@ -463,6 +511,11 @@ gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_ru
       gsgp_destroy(h);
       return fail(GSGP_ERR_NONFINITE, "run %d: X or y holds NaN/Inf (or |y| > FLT_MAX)", i);
     }
+  }
+  if (check_guards(h, GSGP_OK) != GSGP_OK) {
+    const std::string why = g_last_error;
+    gsgp_destroy(h);
+    return fail(GSGP_ERR_STATE, "gsgp_init: %s", why.c_str());
   }
   *out = h;
   return GSGP_OK;
@@ -534,11 +587,11 @@ gsgp_status eval_impl(gsgp_handle* h, const int32_t* h_codes, const double* h_co
 
 }  // namespace
 
-gsgp_status gsgp_eval_population(gsgp_handle* h, const int32_t* h_codes, const double* h_consts) {
+static gsgp_status eval_population_body(gsgp_handle* h, const int32_t* h_codes, const double* h_consts) {
   return eval_impl(h, h_codes, h_consts, nullptr);
 }
 
-gsgp_status gsgp_time_eval(gsgp_handle* h, double* h_ms) {
+static gsgp_status time_eval_body(gsgp_handle* h, double* h_ms) {
   gsgp_status st = usable(h);
   if (st != GSGP_OK) return st;
   if (!h_ms) return fail(GSGP_ERR_ARG, "h_ms is NULL");
@@ -572,7 +625,7 @@ gsgp_status gsgp_time_eval(gsgp_handle* h, double* h_ms) {
   return st;
 }
 
-gsgp_status gsgp_generation(gsgp_handle* h, int32_t n_gens, gsgp_gen_stats* h_stats) {
+static gsgp_status generation_body(gsgp_handle* h, int32_t n_gens, gsgp_gen_stats* h_stats) {
   gsgp_status st = usable(h);
   if (st != GSGP_OK) return st;
   if (!h->evaluated) return fail(GSGP_ERR_STATE, "gsgp_eval_population has not run");
@@ -586,8 +639,8 @@ gsgp_status gsgp_generation(gsgp_handle* h, int32_t n_gens, gsgp_gen_stats* h_st
   return GSGP_OK;
 }
 
-gsgp_status gsgp_generation_replay(gsgp_handle* h, int32_t n_gens, const gsgp_record* h_records,
-                                   const gsgp_gen_stats* h_elite, gsgp_gen_stats* h_stats) {
+static gsgp_status generation_replay_body(gsgp_handle* h, int32_t n_gens, const gsgp_record* h_records,
+                                          const gsgp_gen_stats* h_elite, gsgp_gen_stats* h_stats) {
   gsgp_status st = usable(h);
   if (st != GSGP_OK) return st;
   if (!h->evaluated) return fail(GSGP_ERR_STATE, "gsgp_eval_population has not run");
@@ -724,7 +777,7 @@ gsgp_status gsgp_get_genomes(gsgp_handle* h, int32_t run, int32_t* h_codes, doub
   return GSGP_OK;
 }
 
-gsgp_status gsgp_time_stages(gsgp_handle* h, int32_t n_gens, double* h_ms) {
+static gsgp_status time_stages_body(gsgp_handle* h, int32_t n_gens, double* h_ms) {
   gsgp_status st = usable(h);
   if (st != GSGP_OK) return st;
   if (!h->evaluated) return fail(GSGP_ERR_STATE, "gsgp_eval_population has not run");
@@ -799,7 +852,7 @@ gsgp_status gsgp_set_launch(gsgp_handle* h, int32_t waves_per_block, int32_t off
   return GSGP_OK;
 }
 
-gsgp_status gsgp_autotune(gsgp_handle* h, int32_t* h_best) {
+static gsgp_status autotune_body(gsgp_handle* h, int32_t* h_best) {
   gsgp_status st = usable(h);
   if (st != GSGP_OK) return st;
   if (!h->evaluated) return fail(GSGP_ERR_STATE, "gsgp_eval_population has not run");
@@ -1081,6 +1134,39 @@ gsgp_status gsgp_reconstruct(gsgp_handle* h, int32_t run, int32_t gen, int32_t i
   const int32_t slot = (int32_t)(std::lower_bound(last.begin(), last.end(), individual) - last.begin());
   HIPCHK(h, hipMemcpyAsync(d_out, cur + (int64_t)slot * L.ld, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  return GSGP_OK;
+}
+
+
+// The entry points that launch kernels check the workspace guards
+// (GSGP_FLAG_GUARDS) before returning.
+gsgp_status gsgp_eval_population(gsgp_handle* h, const int32_t* h_codes, const double* h_consts) {
+  return check_guards(h, eval_population_body(h, h_codes, h_consts));
+}
+
+gsgp_status gsgp_time_eval(gsgp_handle* h, double* h_ms) { return check_guards(h, time_eval_body(h, h_ms)); }
+
+gsgp_status gsgp_generation(gsgp_handle* h, int32_t n_gens, gsgp_gen_stats* h_stats) {
+  return check_guards(h, generation_body(h, n_gens, h_stats));
+}
+
+gsgp_status gsgp_generation_replay(gsgp_handle* h, int32_t n_gens, const gsgp_record* h_records,
+                                   const gsgp_gen_stats* h_elite, gsgp_gen_stats* h_stats) {
+  return check_guards(h, generation_replay_body(h, n_gens, h_records, h_elite, h_stats));
+}
+
+gsgp_status gsgp_time_stages(gsgp_handle* h, int32_t n_gens, double* h_ms) {
+  return check_guards(h, time_stages_body(h, n_gens, h_ms));
+}
+
+gsgp_status gsgp_autotune(gsgp_handle* h, int32_t* h_best) { return check_guards(h, autotune_body(h, h_best)); }
+
+gsgp_status gsgp_guard_offsets(gsgp_handle* h, int64_t* h_offsets, int32_t max, int32_t* n) {
+  if (!h) return fail(GSGP_ERR_ARG, "handle is NULL");
+  if (!n || (max > 0 && !h_offsets) || max < 0) return fail(GSGP_ERR_ARG, "bad output arguments");
+  const int32_t total = (int32_t)h->plan.guards.size();
+  *n = total;
+  for (int32_t i = 0; i < total && i < max; ++i) h_offsets[i] = (int64_t)h->plan.guards[i].at;
   return GSGP_OK;
 }
 

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libgsgp.so")
 FP64, FP32, FP32_KAHAN = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp32_kahan": FP32_KAHAN}
 FLAG_NO_GRAPH = 1
+FLAG_GUARDS = 2
 
 STATUS = {0: "GSGP_OK", -1: "GSGP_ERR_ARG", -2: "GSGP_ERR_STATE", -3: "GSGP_ERR_WORKSPACE",
           -4: "GSGP_ERR_NONFINITE", -5: "GSGP_ERR_HIP", -6: "GSGP_ERR_UNSUPPORTED"}
@@ -36,7 +37,7 @@ EXPORTS = [
     "gsgp_current_generation", "gsgp_get_fitness", "gsgp_get_semantics", "gsgp_get_semantics_rows",
     "gsgp_get_records",
     "gsgp_get_stats", "gsgp_get_genomes", "gsgp_time_stages", "gsgp_time_eval", "gsgp_set_launch",
-    "gsgp_autotune", "gsgp_destroy", "gsgp_status_string", "gsgp_last_error",
+    "gsgp_autotune", "gsgp_guard_offsets", "gsgp_destroy", "gsgp_status_string", "gsgp_last_error",
 ]
 
 
@@ -100,6 +101,7 @@ def lib():
             "gsgp_time_eval": [P, P],
             "gsgp_set_launch": [P, I32, I32, I32, I32],
             "gsgp_autotune": [P, P],
+            "gsgp_guard_offsets": [P, P, I32, P],
             "gsgp_destroy": [P],
         }
         for name, args in sig.items():
@@ -359,6 +361,16 @@ class Runner:
                    max_blocks: int = 0) -> None:
         check(lib().gsgp_set_launch(self._h, waves, offspring_per_block, xcd_remap, max_blocks),
               "gsgp_set_launch")
+
+    def guard_offsets(self) -> np.ndarray:
+        """Workspace offsets of the guards (FLAG_GUARDS), relative to the
+        workspace start."""
+        n = ctypes.c_int32(0)
+        check(lib().gsgp_guard_offsets(self._h, None, 0, ctypes.byref(n)), "gsgp_guard_offsets")
+        out = np.zeros(n.value, dtype=np.int64)
+        if n.value:
+            check(lib().gsgp_guard_offsets(self._h, _ptr(out), n.value, ctypes.byref(n)), "gsgp_guard_offsets")
+        return out
 
     def autotune(self):
         best = np.zeros(4, np.int32)

@@ -52,6 +52,16 @@ def test_workspace_size_tracks_memory_complexity():
     assert 1.9 * one < two < 2.1 * one
 
 
+def test_guard_flag_adds_one_guard_per_buffer():
+    """GSGP_FLAG_GUARDS: 3 shared buffers plus 18 per run, each followed by
+    a 256-byte guard (rounded up to the 256-byte buffer alignment)."""
+    for runs in ([(500, 200, 8)], [(500, 200, 8), (900, 0, 3)]):
+        plain = gsgp.workspace_size(gsgp.Settings(), runs)
+        guarded = gsgp.workspace_size(gsgp.Settings(flags=gsgp.FLAG_GUARDS), runs)
+        n_guards = 3 + 18 * len(runs)
+        assert plain + 256 * n_guards <= guarded <= plain + 512 * n_guards
+
+
 BAD_SETTINGS = [
     dict(pop_size=0), dict(pool_size=0), dict(genome_len=0), dict(genome_len=5000),
     dict(n_generations_max=0), dict(tournament_size=-1), dict(tournament_size=65),
@@ -59,6 +69,7 @@ BAD_SETTINGS = [
     dict(tournament_size=0, p_crossover=0.5), dict(mutation_step=-1.0),
     dict(mutation_step=float("nan")), dict(p_function=0.9, p_feature=0.2),
     dict(erc_lo=1.0, erc_hi=-1.0), dict(erc_hi=float("inf")), dict(precision=3), dict(flags=4),
+    dict(flags=8),
 ]
 
 

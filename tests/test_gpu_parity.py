@@ -270,6 +270,48 @@ def test_fp32_overflow_fallback_follows_oracle(precision, tsize, pxo):
     R.close()
 
 
+@pytest.mark.parametrize("precision", [gsgp.FP64, gsgp.FP32])
+def test_operator_identities_on_gpu(precision):
+    """Replayed draws that make each operator an identity: mutation with
+    R1 = R2 and mutation with step 0 return the parent bit for bit;
+    crossover of a parent with itself returns it to 1 ulp; no survival copy
+    is made.  FP64: the identity rows also equal the oracle's parents bit for
+    bit (the crossover rows depend on the pool's exp rounding, so they are
+    held to the ulp bound only)."""
+    d = dataset(700, 300, 4, seed=17)
+    m, r = 30, 9
+    s = gsgp.Settings(pop_size=m, pool_size=r, n_generations_max=1, seed=23, precision=precision)
+    R = _runner(s, [d])
+    R.eval_population()
+    S0 = R.semantics(0, 0)
+    rec = np.zeros((1, m), dtype=gsgp.RECORD_DTYPE)
+    for i in range(m):
+        if i % 3 == 0:
+            rec[0][i] = (0, i, -1, i % r, i % r, 0, 0.3)          # R1 == R2
+        elif i % 3 == 1:
+            rec[0][i] = (0, i, -1, (i + 1) % r, i % r, 0, 0.0)    # step 0
+        else:
+            rec[0][i] = (1, i, i, i % r, -1, 0, 0.0)              # T with itself
+    el = np.zeros(1, dtype=gsgp.STATS_DTYPE)                     # keep every offspring
+    R.replay(rec, el)
+    S1 = R.semantics(0, 0)
+    mut = np.arange(m) % 3 != 2
+    assert np.array_equal(S1[mut], S0[mut])
+    xo = ~mut
+    ulp = np.spacing(np.abs(S0[xo]).astype(np.float64 if precision == gsgp.FP64 else np.float32))
+    assert np.all(np.abs(S1[xo] - S0[xo]) <= ulp)
+    if precision == gsgp.FP64:
+        codes, consts = R.genomes(0)
+        X = np.concatenate([d.X_train, d.X_test])
+        S = orc.interpret(codes[:m], consts[:m], X)
+        sig = orc.sigmoid(orc.interpret(codes[m:], consts[m:], X))
+        orec = np.zeros(m, dtype=orc.RECORD_DTYPE)
+        for f in ("op", "p1", "p2", "r1", "r2", "ms"):
+            orec[f] = rec[0][f]
+        assert np.array_equal(S1[mut], orc.vary(orec, S, sig)[mut])
+    R.close()
+
+
 def test_fp64_replay_of_oracle_lineage_matches():
     d = dataset(800, 200, 5, seed=2)
     G = 10
@@ -411,6 +453,41 @@ def test_autotune_does_not_advance_or_change_the_run():
     (fa, sa, ta), (fb, sb, tb) = out
     assert np.array_equal(fa[0], fb[0]) and np.array_equal(fa[1], fb[1])
     assert np.array_equal(sa, sb) and np.array_equal(ta, tb)
+
+
+@pytest.mark.parametrize("precision", [gsgp.FP64, gsgp.FP32_KAHAN])
+def test_workspace_guards_stay_intact_and_catch_an_overwrite(precision):
+    """With GSGP_FLAG_GUARDS every entry point that launches kernels checks
+    a guard pattern after every workspace buffer: a batched run of ragged
+    sizes goes through set-up, graph and plain generations, a replay,
+    stage timing and autotuning with every guard intact; a guard written
+    from the host is then reported (naming the buffer) and poisons the
+    handle."""
+    ds = [dataset(1500, 77, 4, seed=40), dataset(63, 1, 2, seed=41), dataset(3000, 0, 5, seed=42)]
+    s = gsgp.Settings(pop_size=40, pool_size=24, n_generations_max=14, seed=6, precision=precision,
+                      flags=gsgp.FLAG_GUARDS)
+    R = _runner(s, ds)
+    R.eval_population()
+    R.generation(3)
+    rec = np.stack([R.records(j, 1, 3) for j in range(3)])
+    R.eval_population()
+    R.replay(rec)
+    R.time_stages(2)
+    R.autotune()
+    R.time_eval()
+    R.generation(5)
+    offs = R.guard_offsets()
+    assert offs.size == 3 + 18 * 3
+    base = R._ws_ptr - R._ws.data_ptr()
+    at = int(base + offs[3 + 18 + 2])  # after S[0] of run 1
+    R._ws[at:at + 4] = 0
+    R.torch.cuda.synchronize()
+    with pytest.raises(gsgp.GSGPError) as e:
+        R.generation(1)
+    assert e.value.status == -2 and "S[0] of run 1" in str(e.value)
+    with pytest.raises(gsgp.GSGPError):
+        R.fitness(0)
+    R.close()
 
 
 def test_error_paths():

@@ -555,3 +555,29 @@ def test_export_linear_evaluates_to_the_lineage(orc):
     with pytest.raises(ValueError):
         for i in range(8):
             orc.export_linear(res2, cfg2, 6, i)
+
+
+def test_resume_from_a_saved_state_is_bit_exact(orc):
+    """Checkpoint / resume: the state after generation g (population
+    semantics and fitness; the pool and the data do not change) and the
+    generation index determine the rest of the run, because every draw of
+    generation g' comes from counter (offspring, word block, g', 3).  A run
+    continued by hand from generation 6 equals the straight run bit for bit."""
+    cfg = orc.Config(pop_size=20, pool_size=12, seed=41)
+    Xtr, ytr, Xte, yte = _small_data(n_tr=30, n_te=10, seed=6)
+    G, g0 = 12, 6
+    full = orc.run(cfg, Xtr, ytr, Xte, yte, G, keep_semantics=True)
+    S_tr, S_te = (a.copy() for a in full.S_hist[g0])
+    F, Ft = full.F_hist[g0].copy(), full.Ft_hist[g0].copy()
+    m = cfg.pop_size
+    R_tr, R_te = full.sigR_train, full.sigR_test
+    for g in range(g0 + 1, G + 1):
+        rec = orc.select(cfg, g, F)
+        assert np.array_equal(rec, full.records[g - 1]), g
+        O_tr, O_te = orc.vary(rec, S_tr, R_tr), orc.vary(rec, S_te, R_te)
+        F_O, Ft_O = orc.rmse_rows(O_tr, ytr), orc.rmse_rows(O_te, yte)
+        elite = orc.survive(F, Ft, F_O, Ft_O, S_tr, O_tr, S_te, O_te)
+        assert tuple(elite) == tuple(int(v) for v in full.elite[g - 1]), g
+        S_tr, S_te, F, Ft = O_tr, O_te, F_O, Ft_O
+    assert np.array_equal(S_tr, full.S_train) and np.array_equal(S_te, full.S_test)
+    assert np.array_equal(F, full.F) and np.array_equal(Ft, full.Ft)
