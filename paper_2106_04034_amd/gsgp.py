@@ -14,7 +14,9 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgsgp.so")
+# GSGP_LIBRARY selects another build of the same library (e.g. one with
+# host-side sanitizers); by default the in-tree libgsgp.so.
+LIB_PATH = os.environ.get("GSGP_LIBRARY") or os.path.join(_HERE, "libgsgp.so")
 
 FP64, FP32, FP32_KAHAN = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp32_kahan": FP32_KAHAN}

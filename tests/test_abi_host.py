@@ -121,3 +121,31 @@ def test_null_handle_calls_fail_cleanly():
     assert L.gsgp_generation(None, 1, None) == -1
     assert L.gsgp_eval_population(None, None, None) == -1
     assert L.gsgp_destroy(None) == 0
+
+
+def test_host_code_under_address_sanitizer(tmp_path):
+    """The library's host code (argument validation, workspace planning,
+    handle set-up up to the first device call) built with AddressSanitizer
+    on the host side only: the checks above run clean against it."""
+    import shutil
+    import subprocess
+    import sys
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    rt = "/opt/rocm/llvm/lib/clang/22/lib/linux/libclang_rt.asan-x86_64.so"
+    if not os.path.exists(hipcc) or not os.path.exists(rt):
+        pytest.skip("hipcc or the clang AddressSanitizer runtime is not available")
+    lib = str(tmp_path / "libgsgp_asan.so")
+    csrc = os.path.join(ROOT, "paper_2106_04034_amd", "csrc")
+    # the sanitizer applies to the host pass only (-Xarch_host before it)
+    host_only = "-Xarch_host -fsanitize=address -Xarch_host -fno-omit-frame-pointer -shared-libasan".split()
+    subprocess.check_call([hipcc, "--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC", "-shared",
+                           "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                           *host_only, "-o", lib, os.path.join(csrc, "kernels.hip"),
+                           os.path.join(csrc, "runtime.hip")], stderr=subprocess.DEVNULL)
+    env = dict(os.environ, LD_PRELOAD=rt, GSGP_LIBRARY=lib,
+               ASAN_OPTIONS="detect_leaks=0:alloc_dealloc_mismatch=0:detect_odr_violation=0")
+    out = subprocess.run([sys.executable, "-m", "pytest", "-q", "-p", "no:cacheprovider",
+                          os.path.join(ROOT, "tests", "test_abi_host.py"), "-k", "not sanitizer"],
+                         cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert out.returncode == 0, (out.stdout[-3000:], out.stderr[-3000:])
+    assert "AddressSanitizer" not in out.stderr

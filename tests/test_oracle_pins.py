@@ -581,3 +581,24 @@ def test_resume_from_a_saved_state_is_bit_exact(orc):
         S_tr, S_te, F, Ft = O_tr, O_te, F_O, Ft_O
     assert np.array_equal(S_tr, full.S_train) and np.array_equal(S_te, full.S_test)
     assert np.array_equal(F, full.F) and np.array_equal(Ft, full.Ft)
+
+
+def test_oracle_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+    """The oracle's C code built with AddressSanitizer and UBSan runs a
+    small GSGP loop (ragged sizes, tournaments, crossover, the mutate-all
+    loop with random steps, a one-case test segment) without a report."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc is not available")
+    exe = str(tmp_path / "oracle_sanitized")
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_sanitize_driver.c")
+    osrc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "gsgp_oracle.c")
+    subprocess.check_call([gcc, "-std=c99", "-O1", "-g", "-fno-omit-frame-pointer", "-ffp-contract=off",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                           "-o", exe, src, osrc, "-lm"])
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
+    out = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=120)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert "sanitized oracle ok" in out.stdout
