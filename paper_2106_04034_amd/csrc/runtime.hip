@@ -1161,6 +1161,149 @@ gsgp_status gsgp_time_stages(gsgp_handle* h, int32_t n_gens, double* h_ms) {
 
 gsgp_status gsgp_autotune(gsgp_handle* h, int32_t* h_best) { return check_guards(h, autotune_body(h, h_best)); }
 
+// ---- checkpoint / resume ---------------------------------------------------
+// A checkpoint holds, per run, the current population semantics and fitness,
+// the squashed pool, the genomes and their compiled form, the ancestry record
+// (draws of generations 1 .. gen + 1, summaries 0 .. gen) and the state
+// words; every later draw is a function of (seed, run, offspring, generation)
+// and the fitness, so a loaded handle continues bit for bit.
+namespace {
+
+constexpr uint64_t kCkptMagic = 0x5450434B50475347ull;  // "GSGPCKPT"
+
+struct CkptHeader {
+  uint64_t magic;
+  int32_t version, n_runs, m, r, k, G, precision, gen, slots, pad;
+  uint32_t seed, flags;
+};
+
+struct CkptPiece {
+  size_t off;    // workspace offset
+  size_t bytes;
+};
+
+std::vector<CkptPiece> ckpt_pieces(const gsgp_handle* h) {
+  std::vector<CkptPiece> out;
+  const int64_t m = h->cfg.pop_size, r = h->cfg.pool_size, k = h->cfg.genome_len;
+  const int64_t G = h->cfg.n_generations_max;
+  const size_t s = storage_bytes(h->cfg.precision);
+  const int cur = h->gen & 1;
+  const int64_t n_rec = std::min<int64_t>(h->gen + 1, G);
+  out.push_back({h->plan.state, sizeof(int32_t) * kStWords * h->n_runs});
+  for (int32_t i = 0; i < h->n_runs; ++i) {
+    const RunPlan& q = h->plan.runs[i];
+    out.push_back({cur ? q.S1 : q.S0, s * m * q.ld});
+    out.push_back({q.sigR, s * r * q.ld});
+    out.push_back({cur ? q.F1 : q.F0, 8 * (size_t)m});
+    out.push_back({cur ? q.Ft1 : q.Ft0, 8 * (size_t)m});
+    out.push_back({q.rec, sizeof(gsgp_record) * (size_t)(n_rec * m)});
+    out.push_back({q.stats, sizeof(gsgp_gen_stats) * (size_t)(h->gen + 1)});
+    out.push_back({q.code, 4 * (size_t)((m + r) * k)});
+    out.push_back({q.cval, 8 * (size_t)((m + r) * k)});
+    out.push_back({q.ops, 4 * (size_t)((m + r) * k)});
+    out.push_back({q.opv, 8 * (size_t)((m + r) * k)});
+    out.push_back({q.nops, 4 * (size_t)(m + r)});
+  }
+  return out;
+}
+
+CkptHeader ckpt_header(const gsgp_handle* h) {
+  CkptHeader c{};
+  c.magic = kCkptMagic;
+  c.version = 1;
+  c.n_runs = h->n_runs;
+  c.m = h->cfg.pop_size;
+  c.r = h->cfg.pool_size;
+  c.k = h->cfg.genome_len;
+  c.G = h->cfg.n_generations_max;
+  c.precision = h->cfg.precision;
+  c.gen = h->gen;
+  c.slots = h->slots;
+  c.seed = h->cfg.seed;
+  c.flags = h->cfg.flags;
+  return c;
+}
+
+size_t ckpt_bytes(const gsgp_handle* h, const std::vector<CkptPiece>& pieces) {
+  size_t total = sizeof(CkptHeader) + sizeof(int64_t) * 2 * h->n_runs;  // header, per-run (ld, l)
+  for (const CkptPiece& p : pieces) total += p.bytes;
+  return total;
+}
+
+}  // namespace
+
+gsgp_status gsgp_checkpoint_size(gsgp_handle* h, size_t* bytes) {
+  gsgp_status st = usable(h);
+  if (st != GSGP_OK) return st;
+  if (!bytes) return fail(GSGP_ERR_ARG, "bytes is NULL");
+  if (!h->evaluated) return fail(GSGP_ERR_STATE, "gsgp_eval_population has not run");
+  *bytes = ckpt_bytes(h, ckpt_pieces(h));
+  return GSGP_OK;
+}
+
+gsgp_status gsgp_checkpoint_save(gsgp_handle* h, void* h_buf, size_t bytes) {
+  gsgp_status st = usable(h);
+  if (st != GSGP_OK) return st;
+  if (!h_buf) return fail(GSGP_ERR_ARG, "h_buf is NULL");
+  if (!h->evaluated) return fail(GSGP_ERR_STATE, "gsgp_eval_population has not run");
+  const std::vector<CkptPiece> pieces = ckpt_pieces(h);
+  const size_t need = ckpt_bytes(h, pieces);
+  if (bytes < need) return fail(GSGP_ERR_ARG, "checkpoint buffer has %zu bytes, needs %zu", bytes, need);
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  char* out = (char*)h_buf;
+  const CkptHeader c = ckpt_header(h);
+  std::memcpy(out, &c, sizeof c);
+  out += sizeof c;
+  for (int32_t i = 0; i < h->n_runs; ++i) {
+    const int64_t shape[2] = {h->plan.runs[i].ld, h->plan.runs[i].l};
+    std::memcpy(out, shape, sizeof shape);
+    out += sizeof shape;
+  }
+  for (const CkptPiece& p : pieces) {
+    HIPCHK(h, hipMemcpy(out, h->ws + p.off, p.bytes, hipMemcpyDeviceToHost));
+    out += p.bytes;
+  }
+  return GSGP_OK;
+}
+
+gsgp_status gsgp_checkpoint_load(gsgp_handle* h, const void* h_buf, size_t bytes) {
+  gsgp_status st = usable(h);
+  if (st != GSGP_OK) return st;
+  if (!h_buf || bytes < sizeof(CkptHeader)) return fail(GSGP_ERR_ARG, "no checkpoint");
+  CkptHeader c;
+  std::memcpy(&c, h_buf, sizeof c);
+  if (c.magic != kCkptMagic || c.version != 1) return fail(GSGP_ERR_ARG, "not a checkpoint of this library");
+  if (c.n_runs != h->n_runs || c.m != h->cfg.pop_size || c.r != h->cfg.pool_size || c.k != h->cfg.genome_len ||
+      c.G != h->cfg.n_generations_max || c.precision != h->cfg.precision || c.seed != h->cfg.seed)
+    return fail(GSGP_ERR_ARG, "the checkpoint was taken with another configuration");
+  if (c.gen < 0 || c.gen > h->cfg.n_generations_max || c.slots < 1 || c.slots > kMaxStack)
+    return fail(GSGP_ERR_ARG, "corrupt checkpoint header");
+  const char* in = (const char*)h_buf + sizeof c;
+  if (bytes < sizeof c + sizeof(int64_t) * 2 * h->n_runs) return fail(GSGP_ERR_ARG, "truncated checkpoint");
+  for (int32_t i = 0; i < h->n_runs; ++i) {
+    int64_t shape[2];
+    std::memcpy(shape, in, sizeof shape);
+    in += sizeof shape;
+    if (shape[0] != h->plan.runs[i].ld || shape[1] != h->plan.runs[i].l)
+      return fail(GSGP_ERR_ARG, "run %d: the checkpoint was taken on data of another shape", i);
+  }
+  // the pieces depend on the generation: plan them as of the saved one
+  const int32_t keep_gen = h->gen;
+  h->gen = c.gen;
+  const std::vector<CkptPiece> pieces = ckpt_pieces(h);
+  h->gen = keep_gen;
+  if (bytes < ckpt_bytes(h, pieces)) return fail(GSGP_ERR_ARG, "truncated checkpoint");
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  for (const CkptPiece& p : pieces) {
+    HIPCHK(h, hipMemcpy(h->ws + p.off, in, p.bytes, hipMemcpyHostToDevice));
+    in += p.bytes;
+  }
+  h->gen = c.gen;
+  h->slots = c.slots;
+  h->evaluated = true;
+  return check_guards(h, GSGP_OK);
+}
+
 gsgp_status gsgp_guard_offsets(gsgp_handle* h, int64_t* h_offsets, int32_t max, int32_t* n) {
   if (!h) return fail(GSGP_ERR_ARG, "handle is NULL");
   if (!n || (max > 0 && !h_offsets) || max < 0) return fail(GSGP_ERR_ARG, "bad output arguments");

@@ -39,7 +39,8 @@ EXPORTS = [
     "gsgp_current_generation", "gsgp_get_fitness", "gsgp_get_semantics", "gsgp_get_semantics_rows",
     "gsgp_get_records",
     "gsgp_get_stats", "gsgp_get_genomes", "gsgp_time_stages", "gsgp_time_eval", "gsgp_set_launch",
-    "gsgp_autotune", "gsgp_guard_offsets", "gsgp_destroy", "gsgp_status_string", "gsgp_last_error",
+    "gsgp_autotune", "gsgp_checkpoint_size", "gsgp_checkpoint_save", "gsgp_checkpoint_load",
+    "gsgp_guard_offsets", "gsgp_destroy", "gsgp_status_string", "gsgp_last_error",
 ]
 
 
@@ -104,6 +105,9 @@ def lib():
             "gsgp_set_launch": [P, I32, I32, I32, I32],
             "gsgp_autotune": [P, P],
             "gsgp_guard_offsets": [P, P, I32, P],
+            "gsgp_checkpoint_size": [P, P],
+            "gsgp_checkpoint_save": [P, P, ctypes.c_size_t],
+            "gsgp_checkpoint_load": [P, P, ctypes.c_size_t],
             "gsgp_destroy": [P],
         }
         for name, args in sig.items():
@@ -363,6 +367,18 @@ class Runner:
                    max_blocks: int = 0) -> None:
         check(lib().gsgp_set_launch(self._h, waves, offspring_per_block, xcd_remap, max_blocks),
               "gsgp_set_launch")
+
+    def checkpoint(self) -> bytes:
+        """Every run's state at the current generation (see include/gsgp.h)."""
+        size = ctypes.c_size_t(0)
+        check(lib().gsgp_checkpoint_size(self._h, ctypes.byref(size)), "gsgp_checkpoint_size")
+        buf = ctypes.create_string_buffer(size.value)
+        check(lib().gsgp_checkpoint_save(self._h, buf, size.value), "gsgp_checkpoint_save")
+        return buf.raw
+
+    def restore(self, blob: bytes) -> None:
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        check(lib().gsgp_checkpoint_load(self._h, buf, len(blob)), "gsgp_checkpoint_load")
 
     def guard_offsets(self) -> np.ndarray:
         """Workspace offsets of the guards (FLAG_GUARDS), relative to the

@@ -490,6 +490,45 @@ def test_workspace_guards_stay_intact_and_catch_an_overwrite(precision):
     R.close()
 
 
+@pytest.mark.parametrize("precision", [gsgp.FP64, gsgp.FP32_KAHAN])
+def test_checkpoint_resume_is_bit_exact(precision):
+    """Runs checkpointed at generation 5 and continued in a fresh handle
+    (same configuration, same data, no set-up call) match the uninterrupted
+    runs bit for bit: semantics, fitness, summaries, draws and a
+    reconstruction of the best individual; a checkpoint is refused by a
+    handle with another configuration or when truncated."""
+    ds = [dataset(900, 150, 4, seed=50), dataset(130, 0, 3, seed=51)]
+    s = gsgp.Settings(pop_size=36, pool_size=20, n_generations_max=12, seed=9, precision=precision)
+    A = _runner(s, ds)
+    A.eval_population()
+    A.generation(5)
+    blob = A.checkpoint()
+    A.generation(7)
+    B = _runner(s, ds)
+    B.restore(blob)
+    assert B.current_generation() == 5
+    B.generation(7)
+    Xnew = np.random.default_rng(3).uniform(-1, 1, size=(40, 4))
+    for j in range(2):
+        assert np.array_equal(A.semantics(j, 0), B.semantics(j, 0))
+        assert np.array_equal(A.semantics(j, 1), B.semantics(j, 1))
+        for x, y in zip(A.fitness(j), B.fitness(j)):
+            assert np.array_equal(x, y)
+        assert np.array_equal(A.stats(j, 0, 13), B.stats(j, 0, 13))
+        assert records_equal(A.records(j, 1, 12), B.records(j, 1, 12))
+    best = int(A.stats(0, 12, 1)[0]["best_index"])
+    assert np.array_equal(A.reconstruct(0, 12, best, Xnew), B.reconstruct(0, 12, best, Xnew))
+    other = gsgp.Settings(pop_size=36, pool_size=20, n_generations_max=12, seed=10, precision=precision)
+    C = _runner(other, ds)
+    with pytest.raises(gsgp.GSGPError) as e:
+        C.restore(blob)
+    assert e.value.status == -1
+    with pytest.raises(gsgp.GSGPError):
+        B.restore(blob[:len(blob) // 2])
+    for R in (A, B, C):
+        R.close()
+
+
 def test_error_paths():
     d = dataset(100, 20, 3)
     s = gsgp.Settings(pop_size=8, pool_size=4, n_generations_max=2, seed=1)
