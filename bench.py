@@ -327,7 +327,12 @@ def bench_batched(args) -> dict:
 
     B = gsgp.Runner(settings_for(gsgp, wl, G, gsgp.FP32_KAHAN, seed), datasets, stream=stream)
     B.eval_population()
-    tuned = None if args.no_autotune else B.autotune()
+    if args.launch:
+        w, o, x, g = (int(v) for v in args.launch.split(","))
+        B.set_launch(w, o, x, g)
+        tuned = {"waves": w, "offspring_per_block": o, "xcd_remap": x, "max_blocks": g}
+    else:
+        tuned = None if args.no_autotune else B.autotune()
     B.generation(min(G, 3), stats=False)  # warm up graph capture
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -375,8 +380,11 @@ def bench_batched(args) -> dict:
             R.close()
         return total
 
-    t_plain = per_run(gsgp.FP64, gsgp.FLAG_NO_GRAPH)
-    t_single32 = per_run(gsgp.FP32_KAHAN, 0)
+    if args.skip_per_run:  # profiling runs: the batched handle's kernels only
+        t_plain = t_single32 = float("nan")
+    else:
+        t_plain = per_run(gsgp.FP64, gsgp.FLAG_NO_GRAPH)
+        t_single32 = per_run(gsgp.FP32_KAHAN, 0)
     n_all = sum(d.X_train.shape[0] + d.X_test.shape[0] for d in datasets)
     return {"metric": "runs/hour, batched FP32-Kahan vs plain per-run", "value": n_runs * 3600 / t_batched,
             "unit": "runs/hour", "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
@@ -411,18 +419,53 @@ def bench_paper_shape(args, wl) -> dict:
     s = settings_for(gsgp, wl, G, gsgp.FP32, seed)
     s.ms_random = 1
     stream = torch.cuda.Stream()
+    # the variation launch shape, picked by the autotuner on a handle of its own
+    if args.launch:
+        w, o, x, g = (int(v) for v in args.launch.split(","))
+        tuned = {"waves": w, "offspring_per_block": o, "xcd_remap": x, "max_blocks": g}
+    elif args.no_autotune:
+        tuned = None
+    else:
+        T = gsgp.Runner(s, [data], stream=stream)
+        T.eval_population()
+        tuned = T.autotune()
+        T.close()
     torch.cuda.synchronize()
     # Total run time as the paper takes it: host data in, whole run, the
     # final fitness back on the host.
     t0 = time.perf_counter()
     R = gsgp.Runner(s, [data], stream=stream)
+    if tuned:
+        R.set_launch(tuned["waves"], tuned["offspring_per_block"], tuned["xcd_remap"], tuned["max_blocks"])
     R.eval_population()
     R.generation(G, stats=False)
     F_final, _ = R.fitness(0)
     total_s = time.perf_counter() - t0
     ev = R.time_eval()
-    stages = R.time_stages(min(G, 20))
+    ng = min(G, 20)
+    stages = R.time_stages(ng)
+    rec = R.records(0, 1, ng)
+    n_chunks = -(-(-(-wl.n_train // 64) * 64) // (4096 // 4))
+    per_launch = float(np.mean([vary_bytes(rec[g], wl.n_train, 4, wl.pop_size, n_chunks) for g in range(ng)]))
+    achieved = per_launch / (stages["vary_ms"] * 1e-3) / 1e9
     R.close()
+
+    gpu = {"create_population_ms": ev["create_population_ms"], "compute_semantics_ms": ev["compute_semantics_ms"],
+           "generation_ms": stages["generation_ms"], "total_run_ms": total_s * 1e3}
+    out = {"metric": "stage speed-up over the single-thread FP64 oracle (paper's categories)",
+           "value": None, "unit": "x (one generation)",
+           "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": wl.name, "n_train": wl.n_train, "n_features": wl.n_features,
+                      "pop_size": wl.pop_size, "pool_size": wl.pool_size, "genome_len": wl.genome_len,
+                      "generations": G, "loop": "mutate every individual, random step", "precision": "fp32",
+                      "launch": tuned},
+           "gpu": gpu, "best_train_rmse": float(np.min(F_final)),
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "kernel": "k_vary (GSM + chunk partial sums)",
+                        "alg_bytes_per_launch": per_launch, "launch_ms": stages["vary_ms"]},
+           "stages_ms": {k: round(v, 5) for k, v in stages.items()}}
+    if args.no_cpu_baseline:
+        return out
 
     orc.set_threads(1)
     cfg = orc.Config(pop_size=wl.pop_size, pool_size=wl.pool_size, genome_len=wl.genome_len,
@@ -451,20 +494,13 @@ def bench_paper_shape(args, wl) -> dict:
     c_gen = (time.perf_counter() - t) / gens * frac
     orc.set_threads(len(os.sched_getaffinity(0)))
     c_total = c_create + c_sem + G * c_gen                  # resident data: no load time
-    gpu = {"create_population_ms": ev["create_population_ms"], "compute_semantics_ms": ev["compute_semantics_ms"],
-           "generation_ms": stages["generation_ms"], "total_run_ms": total_s * 1e3}
     cpu = {"create_population_ms": c_create * 1e3, "compute_semantics_ms": c_sem * 1e3,
            "generation_ms": c_gen * 1e3, "total_run_ms": c_total * 1e3}
-    return {"metric": "stage speed-up over the single-thread FP64 oracle (paper's categories)",
-            "value": cpu["generation_ms"] / gpu["generation_ms"], "unit": "x (one generation)",
-            "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
-            "config": {"workload": wl.name, "n_train": wl.n_train, "n_features": wl.n_features,
-                       "pop_size": wl.pop_size, "pool_size": wl.pool_size, "genome_len": wl.genome_len,
-                       "generations": G, "loop": "mutate every individual, random step", "precision": "fp32"},
-            "gpu": gpu, "cpu_oracle_1_thread": cpu, "best_train_rmse": float(np.min(F_final)),
-            "speedup": {k: cpu[k] / gpu[k] for k in gpu},
-            "cpu_sample": f"genomes in full; semantics and {gens} generations on 1/{frac} of the cases, "
-                          "scaled linearly in cases"}
+    out.update({"value": cpu["generation_ms"] / gpu["generation_ms"], "cpu_oracle_1_thread": cpu,
+                "speedup": {k: cpu[k] / gpu[k] for k in gpu},
+                "cpu_sample": f"genomes in full; semantics and {gens} generations on 1/{frac} of the cases, "
+                              "scaled linearly in cases"})
+    return out
 
 
 def main() -> int:
@@ -479,6 +515,8 @@ def main() -> int:
     ap.add_argument("--generations", type=int, default=0,
                     help="override the workload's generation count (profiling runs only)")
     ap.add_argument("--runs", type=int, default=0, help="batched_256: number of runs (default 256)")
+    ap.add_argument("--skip-per-run", action="store_true",
+                    help="batched_256: skip the per-run comparison forms (profiling runs only)")
     ap.add_argument("--launch", default="",
                     help="variation launch shape waves,offspring_per_block,xcd_remap,max_blocks "
                          "(skips autotuning)")

@@ -4,8 +4,9 @@
 //   copy   every 16-byte element read once and written once (1R1W);
 //   mix31  three sources read, one destination written, dst = a + b * c:
 //          the access mix of semantic mutation and crossover (3R1W);
+//   mix31nt the same with non-temporal loads;
 //   read   one source read, one float per thread written at the end.
-// Usage: copy_probe [bytes per array] [reps] [copy|mix31|read] [grid]
+// Usage: copy_probe [bytes per array] [reps] [copy|mix31|mix31nt|read] [grid]
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -58,6 +59,28 @@ __global__ __launch_bounds__(kBlock) void mix31_probe(const f4* __restrict__ a, 
   }
 }
 
+__global__ __launch_bounds__(kBlock) void mix31nt_probe(const f4* __restrict__ a, const f4* __restrict__ b,
+                                                      const f4* __restrict__ c, f4* __restrict__ dst, size_t n) {
+  const size_t step = (size_t)gridDim.x * kBlock * kUnroll;
+  for (size_t base = (size_t)blockIdx.x * kBlock * kUnroll + threadIdx.x; base < n; base += step) {
+    f4 x[kUnroll], y[kUnroll], z[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const size_t i = base + (size_t)u * kBlock;
+      if (i < n) {
+        x[u] = __builtin_nontemporal_load(a + i);
+        y[u] = __builtin_nontemporal_load(b + i);
+        z[u] = __builtin_nontemporal_load(c + i);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const size_t i = base + (size_t)u * kBlock;
+      if (i < n) __builtin_nontemporal_store(x[u] + y[u] * z[u], dst + i);
+    }
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void read_probe(const f4* __restrict__ src, float* __restrict__ out, size_t n) {
   const size_t step = (size_t)gridDim.x * kBlock * kUnroll;
   f4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -85,13 +108,13 @@ int main(int argc, char** argv) {
   const int reps = (argc > 2) ? std::atoi(argv[2]) : 10;
   const char* mode = (argc > 3) ? argv[3] : "copy";
   const unsigned grid = (argc > 4) ? (unsigned)std::strtoul(argv[4], nullptr, 10) : 32768u;
-  const int kind = !std::strcmp(mode, "copy") ? 0 : !std::strcmp(mode, "mix31") ? 1 : !std::strcmp(mode, "read") ? 2 : -1;
+  const int kind = !std::strcmp(mode, "copy") ? 0 : !std::strcmp(mode, "mix31") ? 1 : !std::strcmp(mode, "read") ? 2 : !std::strcmp(mode, "mix31nt") ? 3 : -1;
   if (kind < 0 || reps < 1 || grid < 1 || grid > 65536 || bytes < sizeof(f4)) {
-    std::fprintf(stderr, "usage: copy_probe [bytes] [reps>=1] [copy|mix31|read] [grid 1..65536]\n");
+    std::fprintf(stderr, "usage: copy_probe [bytes] [reps>=1] [copy|mix31|mix31nt|read] [grid 1..65536]\n");
     return 2;
   }
   const size_t n = bytes / sizeof(f4);
-  const int nsrc = kind == 1 ? 3 : 1;
+  const int nsrc = (kind == 1 || kind == 3) ? 3 : 1;
   f4* src[3] = {nullptr, nullptr, nullptr};
   f4* dst = nullptr;
   float* out = nullptr;
@@ -110,6 +133,8 @@ int main(int argc, char** argv) {
       hipLaunchKernelGGL(copy_probe, dim3(grid), dim3(kBlock), 0, 0, src[0], dst, n);
     else if (kind == 1)
       hipLaunchKernelGGL(mix31_probe, dim3(grid), dim3(kBlock), 0, 0, src[0], src[1], src[2], dst, n);
+    else if (kind == 3)
+      hipLaunchKernelGGL(mix31nt_probe, dim3(grid), dim3(kBlock), 0, 0, src[0], src[1], src[2], dst, n);
     else
       hipLaunchKernelGGL(read_probe, dim3(grid), dim3(kBlock), 0, 0, src[0], out, n);
   };

@@ -428,10 +428,11 @@ __device__ __forceinline__ void wave_sum_kahan(float& s, float& c) {
 // Sum over one chunk of (o - t)^2 in the canonical order: each lane adds its
 // elements in address order (LaneSse, fed one 16-byte vector at a time as
 // the offspring values are formed), then the wave butterfly (sse_finish).
-// FP32 forms fall back to FP64 when a square overflows; the fallback
-// re-reads the chunk of the row (`row`, already stored by this wave) and of
-// the target (`tgt`) so the offspring values need not stay live across the
-// reduction.
+// FP32 forms fall back to FP64 when a square overflows.  The fallback takes
+// the offspring values from registers (each offspring vector occupies the
+// registers its three operands free) and reads the target chunk again from
+// memory (`tgt`, an L2 hit): converting the target vectors to FP64 ahead of
+// the rare branch would hold 32 more registers for the whole kernel.
 template <typename T, int PREC>
 struct LaneSse {
   typedef typename std::conditional<PREC == GSGP_FP64, double, float>::type A;
@@ -454,8 +455,8 @@ struct LaneSse {
   }
 };
 
-template <typename T, int PREC, int NJ>
-__device__ __forceinline__ double sse_finish(LaneSse<T, PREC> acc, const bool (&ok)[NJ], const T* row,
+template <typename T, int PREC, int NJ, typename VT>
+__device__ __forceinline__ double sse_finish(LaneSse<T, PREC> acc, const bool (&ok)[NJ], const VT (&o)[NJ],
                                              const T* tgt, int lane) {
   constexpr int N = VecOf<T>::N;
   if constexpr (PREC == GSGP_FP64) {
@@ -469,10 +470,6 @@ __device__ __forceinline__ double sse_finish(LaneSse<T, PREC> acc, const bool (&
       total = (double)acc.s - (double)acc.c;
     }
     if (!isfinite(total)) {
-      // Each lane re-reads exactly the elements it stored itself; a
-      // wavefront-scope fence orders those accesses without the L2
-      // write-back and invalidation of a device- or system-scope fence.
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       double s = 0.0;
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
@@ -480,7 +477,7 @@ __device__ __forceinline__ double sse_finish(LaneSse<T, PREC> acc, const bool (&
         const int e = j * kWave * N + lane * N;
 #pragma unroll
         for (int c = 0; c < N; ++c) {
-          const double d = (double)__builtin_nontemporal_load(row + e + c) - (double)tgt[e + c];
+          const double d = (double)o[j][c] - (double)tgt[e + c];
           s += d * d;
         }
       }
@@ -492,12 +489,12 @@ __device__ __forceinline__ double sse_finish(LaneSse<T, PREC> acc, const bool (&
 
 template <typename T, int PREC, int NJ, typename VT>
 __device__ __forceinline__ double chunk_sse(const VT (&o)[NJ], const VT (&t)[NJ], const bool (&ok)[NJ],
-                                            const T* row, const T* tgt, int lane) {
+                                            const T* tgt, int lane) {
   LaneSse<T, PREC> acc;
 #pragma unroll
   for (int j = 0; j < NJ; ++j)
     if (ok[j]) acc.add(o[j], t[j]);
-  return sse_finish<T, PREC, NJ>(acc, ok, row, tgt, lane);
+  return sse_finish<T, PREC, NJ>(acc, ok, o, tgt, lane);
 }
 
 // One offspring's operands for one chunk.  Mutation reads S[p1], sR[r1],
@@ -541,16 +538,18 @@ __device__ __forceinline__ void vary_offspring(const gsgp_record* rc, const T* S
   // Form, clamp, store and accumulate one 16-byte vector at a time, so the
   // operands of a vector die as soon as its offspring value is stored.
   LaneSse<T, PREC> acc;
-  auto emit = [&](int j, VT o) {
+  VT o[NJ];
+  auto emit = [&](int j, VT v) {
     if constexpr (PREC != GSGP_FP64) {
       // a convex combination of two values near +-FLT_MAX can round past it;
       // operands are finite, so a median-of-three clamps exactly
 #pragma unroll
-      for (int c = 0; c < N; ++c) o[c] = __builtin_amdgcn_fmed3f(o[c], (T)-kFltMax, (T)kFltMax);
+      for (int c = 0; c < N; ++c) v[c] = __builtin_amdgcn_fmed3f(v[c], (T)-kFltMax, (T)kFltMax);
     }
+    o[j] = v;
     if (ok[j]) {
-      gstore_nt<VT>(o, dst + j * kWave * N + lane * N);
-      acc.add(o, t[j]);
+      gstore_nt<VT>(v, dst + j * kWave * N + lane * N);
+      acc.add(v, t[j]);
     }
   };
   if (op == 1) {
@@ -562,7 +561,7 @@ __device__ __forceinline__ void vary_offspring(const gsgp_record* rc, const T* S
 #pragma unroll
     for (int j = 0; j < NJ; ++j) emit(j, x[j] + ms * (y[j] - z[j]));
   }
-  const double sse = sse_finish<T, PREC, NJ>(acc, ok, dst, tgt, lane);
+  const double sse = sse_finish<T, PREC, NJ>(acc, ok, o, tgt, lane);
   if (lane == 0) *part_out = sse;
 }
 
@@ -581,7 +580,7 @@ __device__ __forceinline__ void row_partial(const T* row, int lane, int64_t len,
     ok[j] = FULL || e < len;
     o[j] = ok[j] ? gload<VT>(row + e) : VT(0);
   }
-  const double sse = chunk_sse<T, PREC, NJ, VT>(o, t, ok, row, tgt, lane);
+  const double sse = chunk_sse<T, PREC, NJ, VT>(o, t, ok, tgt, lane);
   if (lane == 0) *part_out = sse;
 }
 
