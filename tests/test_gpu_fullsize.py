@@ -7,7 +7,10 @@ that hold at any size:
     FP32, launch 2 x 2, XCD-contiguous order;
   - batched_256: 256 runs of uneven size in one handle, FP32-Kahan, launch
     4 x 8, XCD side-by-side order; three runs are checked (the largest, the
-    smallest and a middle one).
+    smallest and a middle one);
+  - paper_shape_k127 (Section 3.1 shape): 102,400 cases, 1,024 features,
+    m = r = 10,240, the mutate-all loop with a random step, FP32, launch
+    4 x 4, hardware round-robin order.
 
 Bars:
   - genomes: bit-exact (integer draws, constants from the same FP64 ops);
@@ -57,8 +60,9 @@ def _host_record(s, run_id, i, F):
     xo = ts > 0 and W[0] < pyphilox.threshold(s.p_crossover)
     if xo:
         return dict(op=1, p1=winner(W[5:5 + ts]), p2=winner(W[5 + ts:5 + 2 * ts]), r1=pyphilox.below(W[1], r))
+    ms = s.mutation_step * pyphilox.u53(W[3], W[4]) if s.ms_random else s.mutation_step
     return dict(op=0, p1=winner(W[5:5 + ts]) if ts > 0 else i, r1=pyphilox.below(W[1], r),
-                r2=pyphilox.below(W[2], r), ms=s.mutation_step)
+                r2=pyphilox.below(W[2], r), ms=ms)
 
 
 def _row(R, run, which, i):
@@ -186,4 +190,16 @@ def test_batched_full_size():
         # each check advances every run of the handle, so restart for each
         R.eval_population()
         _check_run(R, j, s, datasets[j], np.random.default_rng(100 + j), 16)
+    R.close()
+
+
+def test_paper_shape_full_size():
+    wl = synth.WORKLOADS["paper_shape_k127"]
+    d = synth.paper_shape(wl.n_train, wl.n_features)
+    s = _settings(wl, gsgp.FP32, synth.evolution_seed(5))
+    s.ms_random = 1
+    R = gsgp.Runner(s, [d])
+    R.set_launch(4, 4, 0, 0)
+    R.eval_population()
+    _check_run(R, 0, s, d, np.random.default_rng(5), 24)
     R.close()
