@@ -30,9 +30,18 @@ constexpr int kMaxTournament = 64;
 // in LDS, at most 64 KiB for one wave.
 constexpr int kMaxStack = 65;
 
-// Compiled genome op word: bits 0..2 kind, bits 3..15 stack depth before
-// the op, bits 16..31 feature index.
-enum OpKind : int32_t { kPushFeature = 0, kPushConst = 1, kAdd = 2, kSub = 3, kMul = 4, kDiv = 5 };
+// Compiled genome op word:
+//   bits 0..1   the function (OpFn), or for a push which terminal (OpPush);
+//   bits 2..3   the class (OpClass);
+//   bits 4..15  stack depth before the op (values, top included);
+//   bits 16..31 feature index.
+// A push directly followed by a function it feeds is compiled into one op
+// (kClsFeature / kClsConst) that applies the function to the top of the
+// stack and the terminal, leaving the rest of the stack untouched.
+enum OpClass : int32_t { kClsPush = 0, kClsStack = 1, kClsFeature = 2, kClsConst = 3 };
+enum OpFn : int32_t { kFnAdd = 0, kFnSub = 1, kFnMul = 2, kFnDiv = 3 };
+enum OpPush : int32_t { kPushFeature = 0, kPushConst = 1 };
+constexpr int kOpDepthMax = 0xFFF;
 
 // Per-run device state words.
 enum StateWord : int {

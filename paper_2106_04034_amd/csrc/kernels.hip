@@ -8,7 +8,8 @@
 // art; the mapping here is:
 //   k_genome     one thread per gene, counter-based Philox draws;
 //   k_compile    one thread per genome: drops the functions the interpreter
-//                would skip and the pushes after the last function, and
+//                would skip and the pushes after the last function, fuses
+//                each push with a function that directly consumes it, and
 //                records every op's stack depth;
 //   k_interpret  one wavefront per (program, 128 cases): the compiled
 //                program is wave-uniform (no divergence), lanes own cases,
@@ -227,21 +228,34 @@ __global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs
   int depth = 0, n = 0, last = 0, deepest = 0;
   for (int q = 0; q < p.k; ++q) {
     const int32_t c = code[q];
+    // depths beyond kMaxStack make the runtime reject the genomes before
+    // any interpretation; the cap only keeps the field inside its bits
+    const int dfield = (depth < kOpDepthMax ? depth : kOpDepthMax) << 4;
     if (c >= 0) {
-      ops[n] = kPushFeature | (depth << 3) | (c << 16);
+      ops[n] = (kClsPush << 2) | kPushFeature | dfield | (c << 16);
       opv[n] = 0.0;
       ++n;
       ++depth;
     } else if (c == -5) {
-      ops[n] = kPushConst | (depth << 3);
+      ops[n] = (kClsPush << 2) | kPushConst | dfield;
       opv[n] = cval[q];
       ++n;
       ++depth;
     } else {
-      if (depth < 2) continue;
-      ops[n] = (kAdd + (-1 - c)) | (depth << 3);
-      opv[n] = 0.0;
-      ++n;
+      if (depth < 2) continue;  // skipped by the interpreter
+      const int fn = -1 - c;
+      const int32_t prev = n > 0 ? ops[n - 1] : 0;
+      if (n > 0 && ((prev >> 2) & 3) == kClsPush) {
+        // push b, then op(a, b) with a the value below it: one op on the top
+        // of the stack; the depth field stays the one before the push, the
+        // feature index and the constant stay where the push put them
+        const int cls = (prev & 3) == kPushConst ? kClsConst : kClsFeature;
+        ops[n - 1] = (prev & ~0xF) | (cls << 2) | fn;
+      } else {
+        ops[n] = (kClsStack << 2) | fn | dfield;
+        opv[n] = 0.0;
+        ++n;
+      }
       --depth;
       last = n;
     }
@@ -255,13 +269,14 @@ __global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs
 // "Interpreter").  The op stream is wave-uniform and read with scalar loads,
 // eight ops per batch.  Stack element i of depth d (0 = bottom) lives in
 // registers for the top two (tos = d-1, nos = d-2) and in LDS below them,
-// at stk[(i * V + v) * 64 + lane]; a function reads its new second operand
-// from LDS only after it has produced its result, so the LDS latency falls
-// outside the op's dependency chain.  The value of the program is the
+// at stk[(i * V + v) * 64 + lane]; a function of the top two values reads
+// its new second operand from LDS only after it has produced its result, so
+// the LDS latency falls outside the op's dependency chain.  A fused op (a
+// push the next function consumes) applies the function to tos and the
+// terminal and touches neither nos nor LDS.  The value of the program is the
 // output of its last function (the Out register), 0.0 if none runs.
-// X is feature-major in global memory, row stride ld (lanes whose column is
-// out of range read nothing); one case block's features stay in L2 while
-// the block's programs run.
+// X is feature-major in global memory, row stride ld; one case block's
+// features stay in L2 while the block's programs run.
 template <int V>
 __device__ __forceinline__ void eval_program(const int32_t* ops, const double* opv, int n, const double* X,
                                              int64_t ld, const int64_t (&col)[V], const bool (&ok)[V],
@@ -276,6 +291,17 @@ __device__ __forceinline__ void eval_program(const int32_t* ops, const double* o
     tos[v] = 0.0;
     nos[v] = 0.0;
   }
+  // lanes past the last column read the last column instead (no exec-mask
+  // branches around the loads); their values are never stored
+  int64_t at[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) at[v] = ok[v] ? col[v] : ld - 1;
+  auto feature = [&](int w, double (&x)[V]) {
+    const int f = (int)((uint32_t)w >> 16);
+    const GSGP_GLOBAL double* xg = (const GSGP_GLOBAL double*)X + (int64_t)f * ld;
+#pragma unroll
+    for (int v = 0; v < V; ++v) x[v] = xg[at[v]];
+  };
   for (int j0 = 0; j0 < n; j0 += kBatch) {
     int wv[kBatch];
     double cv[kBatch];
@@ -289,45 +315,61 @@ __device__ __forceinline__ void eval_program(const int32_t* ops, const double* o
     for (int u = 0; u < kBatch; ++u) {
       if (j0 + u >= n) break;
       const int w = wv[u];
-      const int kind = w & 7;
-      const int d = (w >> 3) & 0x1FFF;  // stack depth before the op
-      if (kind <= kPushConst) {
+      const int cls = (w >> 2) & 3;
+      const int fn = w & 3;
+      const int d = (w >> 4) & kOpDepthMax;  // stack depth before the op
+      if (cls == kClsPush) {
         if (d >= 2) {
 #pragma unroll
           for (int v = 0; v < V; ++v) stk[((d - 2) * V + v) * kWave + lane] = nos[v];
         }
 #pragma unroll
         for (int v = 0; v < V; ++v) nos[v] = tos[v];
-        if (kind == kPushFeature) {
-          const int f = (int)((uint32_t)w >> 16);
-          const GSGP_GLOBAL double* xg = (const GSGP_GLOBAL double*)X + (int64_t)f * ld;
-#pragma unroll
-          for (int v = 0; v < V; ++v) tos[v] = ok[v] ? xg[col[v]] : 0.0;
+        if (fn == kPushFeature) {
+          feature(w, tos);
         } else {
 #pragma unroll
           for (int v = 0; v < V; ++v) tos[v] = cv[u];
         }
       } else {
-        // element d-2 (nos) op element d-1 (tos)
-        if (kind == kAdd) {
+        // op(a, b): b is the top of the stack (or the fused terminal), a the
+        // value below it
+        double a[V], b[V];
+        if (cls == kClsStack) {
 #pragma unroll
-          for (int v = 0; v < V; ++v) tos[v] = nos[v] + tos[v];
-        } else if (kind == kSub) {
-#pragma unroll
-          for (int v = 0; v < V; ++v) tos[v] = nos[v] - tos[v];
-        } else if (kind == kMul) {
-#pragma unroll
-          for (int v = 0; v < V; ++v) tos[v] = nos[v] * tos[v];
+          for (int v = 0; v < V; ++v) {
+            a[v] = nos[v];
+            b[v] = tos[v];
+          }
         } else {
 #pragma unroll
-          for (int v = 0; v < V; ++v) tos[v] = (fabs(tos[v]) < 1e-6) ? 1.0 : nos[v] / tos[v];
+          for (int v = 0; v < V; ++v) a[v] = tos[v];
+          if (cls == kClsFeature) {
+            feature(w, b);
+          } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v) b[v] = cv[u];
+          }
+        }
+        if (fn == kFnAdd) {
+#pragma unroll
+          for (int v = 0; v < V; ++v) tos[v] = a[v] + b[v];
+        } else if (fn == kFnSub) {
+#pragma unroll
+          for (int v = 0; v < V; ++v) tos[v] = a[v] - b[v];
+        } else if (fn == kFnMul) {
+#pragma unroll
+          for (int v = 0; v < V; ++v) tos[v] = a[v] * b[v];
+        } else {
+#pragma unroll
+          for (int v = 0; v < V; ++v) tos[v] = (fabs(b[v]) < 1e-6) ? 1.0 : a[v] / b[v];
         }
         // Every operand is finite (finite features and constants, results
         // clamped here, protected division), so min/max clamp exactly as a
         // compare-and-select would.
 #pragma unroll
         for (int v = 0; v < V; ++v) tos[v] = fmin(fmax(tos[v], -kFltMax), kFltMax);
-        if (d >= 3) {
+        if (cls == kClsStack && d >= 3) {
 #pragma unroll
           for (int v = 0; v < V; ++v) nos[v] = stk[((d - 3) * V + v) * kWave + lane];
         }

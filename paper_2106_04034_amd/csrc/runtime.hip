@@ -1167,6 +1167,8 @@ gsgp_status gsgp_autotune(gsgp_handle* h, int32_t* h_best) { return check_guards
 // (draws of generations 1 .. gen + 1, summaries 0 .. gen) and the state
 // words; every later draw is a function of (seed, run, offspring, generation)
 // and the fitness, so a loaded handle continues bit for bit.
+}  // extern "C"
+
 namespace {
 
 constexpr uint64_t kCkptMagic = 0x5450434B50475347ull;  // "GSGPCKPT"
@@ -1210,7 +1212,7 @@ std::vector<CkptPiece> ckpt_pieces(const gsgp_handle* h) {
 CkptHeader ckpt_header(const gsgp_handle* h) {
   CkptHeader c{};
   c.magic = kCkptMagic;
-  c.version = 1;
+  c.version = 2;  // 2: compiled ops carry fused push-function ops
   c.n_runs = h->n_runs;
   c.m = h->cfg.pop_size;
   c.r = h->cfg.pool_size;
@@ -1231,6 +1233,8 @@ size_t ckpt_bytes(const gsgp_handle* h, const std::vector<CkptPiece>& pieces) {
 }
 
 }  // namespace
+
+extern "C" {
 
 gsgp_status gsgp_checkpoint_size(gsgp_handle* h, size_t* bytes) {
   gsgp_status st = usable(h);
@@ -1272,7 +1276,7 @@ gsgp_status gsgp_checkpoint_load(gsgp_handle* h, const void* h_buf, size_t bytes
   if (!h_buf || bytes < sizeof(CkptHeader)) return fail(GSGP_ERR_ARG, "no checkpoint");
   CkptHeader c;
   std::memcpy(&c, h_buf, sizeof c);
-  if (c.magic != kCkptMagic || c.version != 1) return fail(GSGP_ERR_ARG, "not a checkpoint of this library");
+  if (c.magic != kCkptMagic || c.version != 2) return fail(GSGP_ERR_ARG, "not a checkpoint of this library");
   if (c.n_runs != h->n_runs || c.m != h->cfg.pop_size || c.r != h->cfg.pool_size || c.k != h->cfg.genome_len ||
       c.G != h->cfg.n_generations_max || c.precision != h->cfg.precision || c.seed != h->cfg.seed)
     return fail(GSGP_ERR_ARG, "the checkpoint was taken with another configuration");
