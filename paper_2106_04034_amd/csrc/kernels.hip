@@ -226,33 +226,37 @@ __global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs
   int32_t* ops = R.ops + (int64_t)prog * p.k;
   double* opv = R.opv + (int64_t)prog * p.k;
   int depth = 0, n = 0, last = 0, deepest = 0;
+  int32_t prev = 0;  // the last op word written, ops[n - 1]
   for (int q = 0; q < p.k; ++q) {
     const int32_t c = code[q];
     // depths beyond kMaxStack make the runtime reject the genomes before
     // any interpretation; the cap only keeps the field inside its bits
     const int dfield = (depth < kOpDepthMax ? depth : kOpDepthMax) << 4;
     if (c >= 0) {
-      ops[n] = (kClsPush << 2) | kPushFeature | dfield | (c << 16);
+      prev = (kClsPush << 2) | kPushFeature | dfield | (c << 16);
+      ops[n] = prev;
       opv[n] = 0.0;
       ++n;
       ++depth;
     } else if (c == -5) {
-      ops[n] = (kClsPush << 2) | kPushConst | dfield;
+      prev = (kClsPush << 2) | kPushConst | dfield;
+      ops[n] = prev;
       opv[n] = cval[q];
       ++n;
       ++depth;
     } else {
       if (depth < 2) continue;  // skipped by the interpreter
       const int fn = -1 - c;
-      const int32_t prev = n > 0 ? ops[n - 1] : 0;
       if (n > 0 && ((prev >> 2) & 3) == kClsPush) {
         // push b, then op(a, b) with a the value below it: one op on the top
         // of the stack; the depth field stays the one before the push, the
         // feature index and the constant stay where the push put them
         const int cls = (prev & 3) == kPushConst ? kClsConst : kClsFeature;
-        ops[n - 1] = (prev & ~0xF) | (cls << 2) | fn;
+        prev = (prev & ~0xF) | (cls << 2) | fn;
+        ops[n - 1] = prev;
       } else {
-        ops[n] = (kClsStack << 2) | fn | dfield;
+        prev = (kClsStack << 2) | fn | dfield;
+        ops[n] = prev;
         opv[n] = 0.0;
         ++n;
       }
