@@ -63,6 +63,37 @@ def vary_bytes(rec: np.ndarray, n_all: int, s: int, m: int, n_chunks: int) -> in
     return s * n_all * (m + u_p + u_r + 1) + 8 * m * n_chunks + 32 * m
 
 
+FP64_VALU_OPS = 78.6e12 / 2  # FP64 vector operations/s (the vendor FLOP/s counts an FMA as two)
+
+
+def gene_steps(codes: np.ndarray) -> int:
+    """Algorithmic interpreter work of a set of genomes: per genome, the
+    pushes and valid functions up to its last valid function (the genes
+    that shape its output; skipped functions and trailing pushes cost
+    nothing once compiled).  Counted per case."""
+    depth = np.zeros(codes.shape[0], np.int64)
+    ops = np.zeros(codes.shape[0], np.int64)
+    last = np.zeros(codes.shape[0], np.int64)
+    for q in range(codes.shape[1]):
+        c = codes[:, q]
+        push = (c >= 0) | (c == -5)
+        fn = ~push & (depth >= 2)
+        ops += push | fn
+        depth += push.astype(np.int64) - fn.astype(np.int64)
+        last = np.where(fn, ops, last)
+    return int(last.sum())
+
+
+def interpreter_rate(codes: np.ndarray, n_cases: int, ms: float) -> dict:
+    steps = gene_steps(codes) * n_cases
+    rate = steps / (ms * 1e-3)
+    return {"bound": "alu", "gene_steps": steps, "gene_steps_per_s": rate, "peak_fp64_ops_per_s": FP64_VALU_OPS,
+            "frac": rate / FP64_VALU_OPS, "compute_semantics_ms": ms,
+            "note": "one gene-step is one push or one valid function on one case; the peak is the FP64 vector "
+                    "operation rate, while a function step costs about three FP64 operations (the function and "
+                    "the clamp) plus the interpretive dispatch"}
+
+
 def traffic_from_profile(per_launch_alg: float):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel source; None otherwise."""
@@ -186,6 +217,8 @@ def bench_single(args, wl, data, seed) -> dict:
     u = np.array([distinct_rows(rec[g]) for g in range(ng)])
     achieved = per_launch / (stages["vary_ms"] * 1e-3) / 1e9
     traffic = traffic_from_profile(per_launch) if wl.name == "single_fp32_100k" else None
+    codes, _ = R.genomes(0)
+    interp = interpreter_rate(codes, n_all, eval_stages["compute_semantics_ms"])
     gen_rate = m * n_all / (stages["generation_ms"] * 1e-3)
     # per-generation distribution: one graph launch per generation, HIP
     # events on the library stream around each
@@ -226,7 +259,11 @@ def bench_single(args, wl, data, seed) -> dict:
                      "kernel": "k_vary (GSM/GSC + chunk partial sums)",
                      "alg_bytes_per_launch": per_launch, "launch_ms": stages["vary_ms"],
                      "distinct_parent_rows": float(u[:, 0].mean()),
-                     "distinct_pool_rows": float(u[:, 1].mean())},
+                     "distinct_pool_rows": float(u[:, 1].mean()),
+                     # what a kernel without cross-offspring reuse would move:
+                     # three operand rows read and one written per offspring
+                     "operand_stream_GBps": 4 * s_bytes * m * n_all / (stages["vary_ms"] * 1e-3) / 1e9},
+        "interpreter": interp,
         "stages_ms": {k: round(v, 5) for k, v in stages.items()},
         "eval_population_ms": eval_ms,
         "eval_stages_ms": {k: round(v, 5) for k, v in eval_stages.items()},
@@ -448,6 +485,8 @@ def bench_paper_shape(args, wl) -> dict:
     n_chunks = -(-(-(-wl.n_train // 64) * 64) // (4096 // 4))
     per_launch = float(np.mean([vary_bytes(rec[g], wl.n_train, 4, wl.pop_size, n_chunks) for g in range(ng)]))
     achieved = per_launch / (stages["vary_ms"] * 1e-3) / 1e9
+    codes, _ = R.genomes(0)
+    interp = interpreter_rate(codes, wl.n_train, ev["compute_semantics_ms"])
     R.close()
 
     gpu = {"create_population_ms": ev["create_population_ms"], "compute_semantics_ms": ev["compute_semantics_ms"],
@@ -463,6 +502,7 @@ def bench_paper_shape(args, wl) -> dict:
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS, "kernel": "k_vary (GSM + chunk partial sums)",
                         "alg_bytes_per_launch": per_launch, "launch_ms": stages["vary_ms"]},
+           "interpreter": interp,
            "stages_ms": {k: round(v, 5) for k, v in stages.items()}}
     if args.no_cpu_baseline:
         return out

@@ -29,6 +29,10 @@ constexpr int kMaxTournament = 64;
 // interpreter keeps the top two values in registers and depth - 2 per lane
 // in LDS, at most 64 KiB for one wave.
 constexpr int kMaxStack = 65;
+// Programs whose LDS stack needs at most this many values per lane run in
+// the first interpreter pass with a small LDS column per wave (8 waves per
+// SIMD); the few deeper ones run in a second pass sized for the deepest.
+constexpr int kShallowSlots = 5;
 
 // Compiled genome op word:
 //   bits 0..1   the function (OpFn), or for a push which terminal (OpPush);
@@ -51,6 +55,7 @@ enum StateWord : int {
   kStReplayElite = 3,   // 1: survival decisions are supplied
   kStMaxDepth = 4,      // deepest stack of the compiled genomes
   kStNonFinite = 5,     // set when X or y holds NaN / Inf
+  kStDeepCount = 6,     // programs that need more than kShallowSlots LDS values
   kStWords = 8
 };
 
@@ -71,6 +76,8 @@ struct RunDev {
   int32_t* ops;             // compiled genomes, [m + r][k]
   double* opv;              // [m + r][k]
   int32_t* nops;            // [m + r]
+  int32_t* need;            // LDS stack values per lane each program needs, [m + r]
+  int32_t* deep;            // programs with need > kShallowSlots, [m + r] (kStDeepCount used)
   int32_t* state;           // [kStWords]
   int64_t n_train, n_test;  // real cases
   int64_t tr_pad, te_pad;   // padded segment lengths
@@ -153,9 +160,11 @@ hipError_t launch_set_state(const RunDev* d_runs, int32_t n_runs, int32_t word, 
                             hipStream_t s);
 hipError_t launch_genome(const RunDev* d_runs, const Params& p, hipStream_t s);
 hipError_t launch_compile(const RunDev* d_runs, const Params& p, hipStream_t s);
-// slots: stack values per lane kept in LDS (deepest stack - 2, at least 1).
+// slots: stack values per lane kept in LDS (at least 1).  deep_max < 0: the
+// first pass, every program whose need fits in `slots`; deep_max >= 0: the
+// second pass over each run's deep list, at most deep_max programs per run.
 hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_blocks, int slots,
-                            hipStream_t s);
+                            int32_t deep_max, hipStream_t s);
 hipError_t launch_vary(const RunDev* d_runs, const Params& p, const VaryLaunch& lc, bool rows_only,
                        hipStream_t s);
 hipError_t launch_fitness(const RunDev* d_runs, const Params& p, bool init, hipStream_t s);

@@ -266,6 +266,9 @@ __global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs
     deepest = depth > deepest ? depth : deepest;
   }
   R.nops[prog] = last;
+  const int need = deepest > 2 ? deepest - 2 : 0;  // the top two values live in registers
+  R.need[prog] = need;
+  if (need > kShallowSlots) R.deep[atomicAdd(&R.state[kStDeepCount], 1)] = prog;
   atomicMax(&R.state[kStMaxDepth], deepest);
 }
 
@@ -355,24 +358,25 @@ __device__ __forceinline__ void eval_program(const int32_t* ops, const double* o
             for (int v = 0; v < V; ++v) b[v] = cv[u];
           }
         }
-        if (fn == kFnAdd) {
-#pragma unroll
-          for (int v = 0; v < V; ++v) tos[v] = a[v] + b[v];
-        } else if (fn == kFnSub) {
-#pragma unroll
-          for (int v = 0; v < V; ++v) tos[v] = a[v] - b[v];
-        } else if (fn == kFnMul) {
-#pragma unroll
-          for (int v = 0; v < V; ++v) tos[v] = a[v] * b[v];
-        } else {
-#pragma unroll
-          for (int v = 0; v < V; ++v) tos[v] = (fabs(b[v]) < 1e-6) ? 1.0 : a[v] / b[v];
-        }
         // Every operand is finite (finite features and constants, results
         // clamped here, protected division), so min/max clamp exactly as a
-        // compare-and-select would.
+        // compare-and-select would.  The clamp sits in each branch, on the
+        // arithmetic result itself, where the compiler knows the value needs
+        // no NaN canonicalisation before min/max.
+        auto clamp = [](double x) { return fmin(fmax(x, -kFltMax), kFltMax); };
+        if (fn == kFnAdd) {
 #pragma unroll
-        for (int v = 0; v < V; ++v) tos[v] = fmin(fmax(tos[v], -kFltMax), kFltMax);
+          for (int v = 0; v < V; ++v) tos[v] = clamp(a[v] + b[v]);
+        } else if (fn == kFnSub) {
+#pragma unroll
+          for (int v = 0; v < V; ++v) tos[v] = clamp(a[v] - b[v]);
+        } else if (fn == kFnMul) {
+#pragma unroll
+          for (int v = 0; v < V; ++v) tos[v] = clamp(a[v] * b[v]);
+        } else {
+#pragma unroll
+          for (int v = 0; v < V; ++v) tos[v] = clamp((fabs(b[v]) < 1e-6) ? 1.0 : a[v] / b[v]);
+        }
         if (cls == kClsStack && d >= 3) {
 #pragma unroll
           for (int v = 0; v < V; ++v) nos[v] = stk[((d - 3) * V + v) * kWave + lane];
@@ -391,14 +395,18 @@ constexpr int kInterpProgsPerWave = 8;   // programs each wave interprets on its
 
 // ComputeSemantics(P) and ComputeSemantics(R) (Algorithm 1).  A block takes
 // one block of 128 cases of one run and a group of programs; each wave
-// interprets kInterpProgsPerWave programs on the block's cases.  Pool rows
+// interprets kInterpProgsPerWave programs on the block's cases.  The LDS
+// stack column of a wave bounds how many waves a CU holds, and the kernel
+// is latency-bound, so it runs in two passes: every program whose stack
+// fits in kShallowSlots LDS values, then (deep_pass) the run's list of
+// deeper programs with a column sized for the deepest.  Pool rows
 // are squashed by the logistic function (the random functions R_u of GSM,
 // Section 2) before storage.  Padding columns are written as exact zeros.
 // (Staging the case block's features in LDS was slower: the tile cut the
 // number of resident waves more than it saved in L2 reads.)
 template <typename T>
 __global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ runs, Params p, int32_t pgroups,
-                                                   int slots) {
+                                                   int slots, int deep_pass) {
   extern __shared__ double lds[];
   const int lane = threadIdx.x & 63;
   const int wave = uni(threadIdx.x >> 6);
@@ -419,8 +427,16 @@ __global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ ru
     ok[v] = col[v] < ld;
   }
   for (int j = 0; j < kInterpProgsPerWave; ++j) {
-    const int prog = (pg * kInterpProgsPerWave + j) * W + wave;
-    if (prog >= rows) break;
+    const int idx = (pg * kInterpProgsPerWave + j) * W + wave;
+    int prog;
+    if (deep_pass) {
+      if (idx >= uni(cload(&R.state[kStDeepCount]))) break;
+      prog = uni(cload(&R.deep[idx]));
+    } else {
+      if (idx >= rows) break;
+      prog = idx;
+      if (uni(cload(&R.need[prog])) > slots) continue;  // left to the deep pass
+    }
     double out[kInterpV];
     eval_program<kInterpV>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k, uni(cload(&R.nops[prog])),
                            R.X, ld, col, ok, stk, lane, out);
@@ -1159,18 +1175,20 @@ hipError_t launch_compile(const RunDev* d_runs, const Params& p, hipStream_t s) 
 }
 
 hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_blocks, int slots,
-                            hipStream_t s) {
+                            int32_t deep_max, hipStream_t s) {
   if (slots < 1) slots = 1;
+  if (deep_max == 0) return hipSuccess;
   // one LDS stack column block per wave, at most 64 KiB per block
   const int waves = interp_waves(slots);
   const size_t shmem = (size_t)waves * slots * kInterpV * kWave * sizeof(double);
-  const int rows = p.m + p.r;
-  const int32_t pgroups = (rows + waves * kInterpProgsPerWave - 1) / (waves * kInterpProgsPerWave);
+  const int progs = deep_max > 0 ? deep_max : p.m + p.r;
+  const int32_t pgroups = (progs + waves * kInterpProgsPerWave - 1) / (waves * kInterpProgsPerWave);
   const dim3 grid((unsigned)(case_blocks * pgroups)), block(waves * kWave);
+  const int deep_pass = deep_max > 0 ? 1 : 0;
   if (p.precision == GSGP_FP64)
-    hipLaunchKernelGGL((k_interpret<double>), grid, block, shmem, s, d_runs, p, pgroups, slots);
+    hipLaunchKernelGGL((k_interpret<double>), grid, block, shmem, s, d_runs, p, pgroups, slots, deep_pass);
   else
-    hipLaunchKernelGGL((k_interpret<float>), grid, block, shmem, s, d_runs, p, pgroups, slots);
+    hipLaunchKernelGGL((k_interpret<float>), grid, block, shmem, s, d_runs, p, pgroups, slots, deep_pass);
   return hipGetLastError();
 }
 

@@ -51,7 +51,7 @@ size_t storage_bytes(int32_t precision) { return precision == GSGP_FP64 ? 8 : 4;
 struct RunPlan {
   int64_t n_train, n_test, tr_pad, te_pad, ld;
   int32_t l, nch_tr, nch_te;
-  size_t X, y, S0, S1, sigR, part, F0, F1, Ft0, Ft1, rec, stats, elite_in, code, cval, ops, opv, nops;
+  size_t X, y, S0, S1, sigR, part, F0, F1, Ft0, Ft1, rec, stats, elite_in, code, cval, ops, opv, nops, need, deep;
   size_t end;
 };
 
@@ -159,6 +159,8 @@ gsgp_status make_plan(const gsgp_config* c, const gsgp_run* runs, int32_t n_runs
     p.ops = take_at(4 * (m + r) * k, i, "compiled ops");
     p.opv = take_at(8 * (m + r) * k, i, "compiled constants");
     p.nops = take_at(4 * (m + r), i, "program lengths");
+    p.need = take_at(4 * (m + r), i, "program stack needs");
+    p.deep = take_at(4 * (m + r), i, "deep program list");
     p.end = off;
   }
   plan->total = off;
@@ -452,6 +454,8 @@ gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_ru
     R.ops = (int32_t*)(ws + q.ops);
     R.opv = (double*)(ws + q.opv);
     R.nops = (int32_t*)(ws + q.nops);
+    R.need = (int32_t*)(ws + q.need);
+    R.deep = (int32_t*)(ws + q.deep);
     R.state = state + (size_t)kStWords * i;
     R.n_train = q.n_train;
     R.n_test = q.n_test;
@@ -552,7 +556,7 @@ gsgp_status eval_impl(gsgp_handle* h, const int32_t* h_codes, const double* h_co
     }
   }
   if (ev) HIPCHK(h, hipEventRecord(ev[0], h->stream));
-  for (int32_t w : {kStGen, kStDone, kStReplaySelect, kStReplayElite, kStMaxDepth})
+  for (int32_t w : {kStGen, kStDone, kStReplaySelect, kStReplayElite, kStMaxDepth, kStDeepCount})
     HIPCHK(h, launch_set_state(h->runs_d, h->n_runs, w, 0, h->stream));
   if (h_codes) {
     for (int32_t r = 0; r < h->n_runs; ++r) {
@@ -567,14 +571,20 @@ gsgp_status eval_impl(gsgp_handle* h, const int32_t* h_codes, const double* h_co
   int32_t* state = (int32_t*)(h->ws + h->plan.state);
   HIPCHK(h, hipMemcpyAsync(h->pinned, state, sizeof(int32_t) * kStWords * h->n_runs, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  int32_t deepest = 0;
-  for (int32_t r = 0; r < h->n_runs; ++r) deepest = std::max(deepest, h->pinned[kStWords * r + kStMaxDepth]);
+  int32_t deepest = 0, deep_max = 0;
+  for (int32_t r = 0; r < h->n_runs; ++r) {
+    deepest = std::max(deepest, h->pinned[kStWords * r + kStMaxDepth]);
+    deep_max = std::max(deep_max, h->pinned[kStWords * r + kStDeepCount]);
+  }
   if (deepest > kMaxStack) {
     h->evaluated = false;
     return fail(GSGP_ERR_UNSUPPORTED, "a genome needs a stack of %d values; at most %d are supported", deepest, kMaxStack);
   }
   h->slots = std::max(1, deepest - 2);  // the top two values live in registers
-  HIPCHK(h, launch_interpret(h->runs_d, p, h->interp_tasks, h->slots, h->stream));
+  // every program that fits a small LDS column, then the deep ones
+  HIPCHK(h, launch_interpret(h->runs_d, p, h->interp_tasks, std::min(h->slots, kShallowSlots), -1, h->stream));
+  if (h->slots > kShallowSlots)
+    HIPCHK(h, launch_interpret(h->runs_d, p, h->interp_tasks, h->slots, deep_max, h->stream));
   if (ev) HIPCHK(h, hipEventRecord(ev[2], h->stream));
   HIPCHK(h, launch_vary(h->runs_d, p, h->rows, true, h->stream));
   HIPCHK(h, launch_fitness(h->runs_d, p, true, h->stream));

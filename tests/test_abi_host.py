@@ -53,12 +53,12 @@ def test_workspace_size_tracks_memory_complexity():
 
 
 def test_guard_flag_adds_one_guard_per_buffer():
-    """GSGP_FLAG_GUARDS: 3 shared buffers plus 18 per run, each followed by
+    """GSGP_FLAG_GUARDS: 3 shared buffers plus 20 per run, each followed by
     a 256-byte guard (rounded up to the 256-byte buffer alignment)."""
     for runs in ([(500, 200, 8)], [(500, 200, 8), (900, 0, 3)]):
         plain = gsgp.workspace_size(gsgp.Settings(), runs)
         guarded = gsgp.workspace_size(gsgp.Settings(flags=gsgp.FLAG_GUARDS), runs)
-        n_guards = 3 + 18 * len(runs)
+        n_guards = 3 + 20 * len(runs)
         assert plain + 256 * n_guards <= guarded <= plain + 512 * n_guards
 
 

@@ -103,6 +103,75 @@ def test_hand_worked_programs_on_gpu():
     R.close()
 
 
+def _deep_genome(rng, D, k, l):
+    """D terminals then D - 1 functions: a stack D values deep, right-aligned
+    after functions that the interpreter skips (stack too short)."""
+    c = np.full(k, -1, np.int32)
+    v = np.zeros(k)
+    body_c, body_v = [], []
+    for t in range(D):
+        if t % 3 == 2:
+            body_c.append(-5)
+            body_v.append(float(rng.uniform(-1.0, 1.0)))
+        else:
+            body_c.append(int(rng.integers(0, l)))
+            body_v.append(0.0)
+    body_c += [-1 - (t % 4) for t in range(D - 1)]
+    body_v += [0.0] * (D - 1)
+    c[k - len(body_c):] = body_c
+    v[k - len(body_v):] = body_v
+    return c, v
+
+
+def _stack_depths(codes):
+    """Deepest stack of each genome, functions on a short stack skipped."""
+    depth = np.zeros(codes.shape[0], np.int64)
+    deep = np.zeros(codes.shape[0], np.int64)
+    for q in range(codes.shape[1]):
+        c = codes[:, q]
+        push = (c >= 0) | (c == -5)
+        fn = ~push & (depth >= 2)
+        depth += push.astype(np.int64) - fn.astype(np.int64)
+        deep = np.maximum(deep, depth)
+    return deep
+
+
+def test_deep_programs_take_the_second_interpreter_pass():
+    """Programs whose stack needs more LDS values per lane than the first
+    interpreter pass provides run in a second pass.  A population mixing
+    random genomes with stacks 8 to 60 values deep, in a handle with a
+    second run that has (almost) no deep program, matches the oracle bit for
+    bit."""
+    rng = np.random.default_rng(8)
+    k, l, m, r = 128, 4, 40, 12
+    s = gsgp.Settings(pop_size=m, pool_size=r, genome_len=k, n_generations_max=1, seed=31)
+    ds = [dataset(300, 100, l, seed=41), dataset(200, 0, l, seed=42)]
+    codes, consts = [], []
+    for run in range(2):
+        ocfg = oracle_config(s, run_id=run)
+        cp, vp = orc.genomes(ocfg, l, orc.TAG_POPULATION, m)
+        cr, vr = orc.genomes(ocfg, l, orc.TAG_POOL, r)
+        c, v = np.concatenate([cp, cr]), np.concatenate([vp, vr])
+        if run == 0:
+            for row, D in zip((0, 3, 17, 39, m, m + 5), (8, 13, 60, 21, 9, 34)):
+                c[row], v[row] = _deep_genome(rng, D, k, l)
+        codes.append(c)
+        consts.append(v)
+    need = [_stack_depths(c) - 2 for c in codes]
+    # run 0 has many programs that need a deep LDS column, run 1 at most one
+    assert (need[0] > 5).sum() == 6 and (need[1] > 4).sum() <= 1
+    R = _runner(s, ds)
+    R.eval_population(np.concatenate(codes), np.concatenate(consts))
+    for run, d in enumerate(ds):
+        X = np.concatenate([d.X_train, d.X_test])
+        want = orc.interpret(codes[run][:m], consts[run][:m], X)
+        assert np.array_equal(R.semantics(run, 0), want), run
+        sig = orc.sigmoid(orc.interpret(codes[run][m:], consts[run][m:], X))
+        got = R.semantics(run, 1)
+        assert np.all(np.abs(got - sig) <= 4 * np.spacing(np.maximum(np.abs(sig), 1e-300))), run
+    R.close()
+
+
 @pytest.mark.parametrize("n_train,n_test,l", [(1, 0, 1), (63, 1, 2), (513, 0, 3), (1500, 77, 4),
                                                (2048, 512, 7)])
 def test_ragged_and_edge_sizes(n_train, n_test, l):
@@ -477,9 +546,9 @@ def test_workspace_guards_stay_intact_and_catch_an_overwrite(precision):
     R.time_eval()
     R.generation(5)
     offs = R.guard_offsets()
-    assert offs.size == 3 + 18 * 3
+    assert offs.size == 3 + 20 * 3
     base = R._ws_ptr - R._ws.data_ptr()
-    at = int(base + offs[3 + 18 + 2])  # after S[0] of run 1
+    at = int(base + offs[3 + 20 + 2])  # after S[0] of run 1
     R._ws[at:at + 4] = 0
     R.torch.cuda.synchronize()
     with pytest.raises(gsgp.GSGPError) as e:
