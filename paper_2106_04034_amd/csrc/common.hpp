@@ -41,7 +41,9 @@ constexpr int kShallowSlots = 5;
 //   bits 16..31 feature index.
 // A push directly followed by a function it feeds is compiled into one op
 // (kClsFeature / kClsConst) that applies the function to the top of the
-// stack and the terminal, leaving the rest of the stack untouched.
+// stack and the terminal, leaving the rest of the stack untouched.  The op's
+// constant slot holds the constant of a constant op and, for a feature op,
+// the bits of the 64-bit row offset feature * ld in the run's X.
 enum OpClass : int32_t { kClsPush = 0, kClsStack = 1, kClsFeature = 2, kClsConst = 3 };
 enum OpFn : int32_t { kFnAdd = 0, kFnSub = 1, kFnMul = 2, kFnDiv = 3 };
 enum OpPush : int32_t { kPushFeature = 0, kPushConst = 1 };

@@ -235,7 +235,8 @@ __global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs
     if (c >= 0) {
       prev = (kClsPush << 2) | kPushFeature | dfield | (c << 16);
       ops[n] = prev;
-      opv[n] = 0.0;
+      // the feature's row offset in this run's X, bit for bit (see eval_program)
+      opv[n] = __longlong_as_double((long long)c * R.ld);
       ++n;
       ++depth;
     } else if (c == -5) {
@@ -284,7 +285,7 @@ __global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs
 // output of its last function (the Out register), 0.0 if none runs.
 // X is feature-major in global memory, row stride ld; one case block's
 // features stay in L2 while the block's programs run.
-template <int V>
+template <int V, bool BAKED>
 __device__ __forceinline__ void eval_program(const int32_t* ops, const double* opv, int n, const double* X,
                                              int64_t ld, const int64_t (&col)[V], const bool (&ok)[V],
                                              double* stk_lds, int lane, double (&out)[V]) {
@@ -303,9 +304,12 @@ __device__ __forceinline__ void eval_program(const int32_t* ops, const double* o
   int64_t at[V];
 #pragma unroll
   for (int v = 0; v < V; ++v) at[v] = ok[v] ? col[v] : ld - 1;
-  auto feature = [&](int w, double (&x)[V]) {
-    const int f = (int)((uint32_t)w >> 16);
-    const GSGP_GLOBAL double* xg = (const GSGP_GLOBAL double*)X + (int64_t)f * ld;
+  auto feature = [&](int w, double c, double (&x)[V]) {
+    // BAKED: the compile step stored the row offset f * ld of the handle's
+    // own X in the op's constant slot (an integer's bits, never used as a
+    // number); other callers pass an X of their own and use the index
+    const int64_t row = BAKED ? (int64_t)__double_as_longlong(c) : (int64_t)((uint32_t)w >> 16) * ld;
+    const GSGP_GLOBAL double* xg = (const GSGP_GLOBAL double*)X + row;
 #pragma unroll
     for (int v = 0; v < V; ++v) x[v] = xg[at[v]];
   };
@@ -333,7 +337,7 @@ __device__ __forceinline__ void eval_program(const int32_t* ops, const double* o
 #pragma unroll
         for (int v = 0; v < V; ++v) nos[v] = tos[v];
         if (fn == kPushFeature) {
-          feature(w, tos);
+          feature(w, cv[u], tos);
         } else {
 #pragma unroll
           for (int v = 0; v < V; ++v) tos[v] = cv[u];
@@ -352,7 +356,7 @@ __device__ __forceinline__ void eval_program(const int32_t* ops, const double* o
 #pragma unroll
           for (int v = 0; v < V; ++v) a[v] = tos[v];
           if (cls == kClsFeature) {
-            feature(w, b);
+            feature(w, cv[u], b);
           } else {
 #pragma unroll
             for (int v = 0; v < V; ++v) b[v] = cv[u];
@@ -438,7 +442,7 @@ __global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ ru
       if (uni(cload(&R.need[prog])) > slots) continue;  // left to the deep pass
     }
     double out[kInterpV];
-    eval_program<kInterpV>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k, uni(cload(&R.nops[prog])),
+    eval_program<kInterpV, true>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k, uni(cload(&R.nops[prog])),
                            R.X, ld, col, ok, stk, lane, out);
     const bool pool = prog >= p.m;
     T* dst = pool ? (T*)R.sigR : (T*)R.S[0];
@@ -1091,7 +1095,7 @@ __global__ __launch_bounds__(256) void k_interpret_list(const int32_t* __restric
   }
   double val[kInterpV];
   double* stk = lds + wave * slots * kInterpV * kWave;
-  eval_program<kInterpV>(ops + (int64_t)pr * k, opv + (int64_t)pr * k, uni(nops[pr]), Xfm, ld, col, ok, stk, lane,
+  eval_program<kInterpV, false>(ops + (int64_t)pr * k, opv + (int64_t)pr * k, uni(nops[pr]), Xfm, ld, col, ok, stk, lane,
                          val);
   const bool sq = squash[j] != 0;
 #pragma unroll

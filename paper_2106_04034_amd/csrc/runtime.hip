@@ -1222,7 +1222,7 @@ std::vector<CkptPiece> ckpt_pieces(const gsgp_handle* h) {
 CkptHeader ckpt_header(const gsgp_handle* h) {
   CkptHeader c{};
   c.magic = kCkptMagic;
-  c.version = 2;  // 2: compiled ops carry fused push-function ops
+  c.version = 3;  // 3: fused push-function ops, feature row offsets in opv
   c.n_runs = h->n_runs;
   c.m = h->cfg.pop_size;
   c.r = h->cfg.pool_size;
@@ -1286,7 +1286,7 @@ gsgp_status gsgp_checkpoint_load(gsgp_handle* h, const void* h_buf, size_t bytes
   if (!h_buf || bytes < sizeof(CkptHeader)) return fail(GSGP_ERR_ARG, "no checkpoint");
   CkptHeader c;
   std::memcpy(&c, h_buf, sizeof c);
-  if (c.magic != kCkptMagic || c.version != 2) return fail(GSGP_ERR_ARG, "not a checkpoint of this library");
+  if (c.magic != kCkptMagic || c.version != 3) return fail(GSGP_ERR_ARG, "not a checkpoint of this library");
   if (c.n_runs != h->n_runs || c.m != h->cfg.pop_size || c.r != h->cfg.pool_size || c.k != h->cfg.genome_len ||
       c.G != h->cfg.n_generations_max || c.precision != h->cfg.precision || c.seed != h->cfg.seed)
     return fail(GSGP_ERR_ARG, "the checkpoint was taken with another configuration");
