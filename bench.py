@@ -44,7 +44,12 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2106_04034_amd", "csrc", "kernels.hip")
 
 
 def kernel_digest() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """Digest of the device code's sources (the kernels and the header of
+    shared constants and layouts they include)."""
+    h = hashlib.sha256()
+    for path in (KERNEL_SRC, os.path.join(os.path.dirname(KERNEL_SRC), "common.hpp")):
+        h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def distinct_rows(rec: np.ndarray):
