@@ -33,6 +33,9 @@ constexpr int kMaxStack = 65;
 // the first interpreter pass with a small LDS column per wave (8 waves per
 // SIMD); the few deeper ones run in a second pass sized for the deepest.
 constexpr int kShallowSlots = 5;
+// The interpreter reads a program's ops eight at a time; the compiled-op
+// buffers carry this many entries of padding after the last program.
+constexpr int kOpPad = 8;
 
 // Compiled genome op word:
 //   bits 0..1   the function (OpFn), or for a push which terminal (OpPush);
@@ -75,8 +78,8 @@ struct RunDev {
   gsgp_gen_stats* elite_in; // supplied survival decisions, [gmax]
   int32_t* code;            // genomes, [m + r][k]
   double* cval;             // [m + r][k]
-  int32_t* ops;             // compiled genomes, [m + r][k]
-  double* opv;              // [m + r][k]
+  int32_t* ops;             // compiled genomes, [m + r][k] + kOpPad
+  double* opv;              // [m + r][k] + kOpPad
   int32_t* nops;            // [m + r]
   int32_t* need;            // LDS stack values per lane each program needs, [m + r]
   int32_t* deep;            // programs with need > kShallowSlots, [m + r] (kStDeepCount used)

@@ -275,7 +275,7 @@ __global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs
 
 // Evaluate one compiled program on V cases per lane (Section 2.2
 // "Interpreter").  The op stream is wave-uniform and read with scalar loads,
-// eight ops per batch.  Stack element i of depth d (0 = bottom) lives in
+// eight ops per batch in one load of words and one of constants.  Stack element i of depth d (0 = bottom) lives in
 // registers for the top two (tos = d-1, nos = d-2) and in LDS below them,
 // at stk[(i * V + v) * 64 + lane]; a function of the top two values reads
 // its new second operand from LDS only after it has produced its result, so
@@ -289,7 +289,7 @@ template <int V, bool BAKED>
 __device__ __forceinline__ void eval_program(const int32_t* ops, const double* opv, int n, const double* X,
                                              int64_t ld, const int64_t (&col)[V], const bool (&ok)[V],
                                              double* stk_lds, int lane, double (&out)[V]) {
-  constexpr int kBatch = 8;
+  constexpr int kBatch = kOpPad;
   const GSGP_CONST int32_t* cops = (const GSGP_CONST int32_t*)ops;
   const GSGP_CONST double* copv = (const GSGP_CONST double*)opv;
   GSGP_LDS double* stk = (GSGP_LDS double*)stk_lds;
@@ -318,9 +318,11 @@ __device__ __forceinline__ void eval_program(const int32_t* ops, const double* o
     double cv[kBatch];
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
-      const int j = j0 + u < n ? j0 + u : n - 1;  // stay inside this program's ops
-      wv[u] = cops[j];
-      cv[u] = copv[j];
+      // one contiguous batch (two scalar loads); the last batch of a program
+      // may read up to kBatch - 1 words past it, which the buffers' padding
+      // after the last program keeps in bounds, and never uses them
+      wv[u] = cops[j0 + u];
+      cv[u] = copv[j0 + u];
     }
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {

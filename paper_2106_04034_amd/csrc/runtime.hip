@@ -156,8 +156,8 @@ gsgp_status make_plan(const gsgp_config* c, const gsgp_run* runs, int32_t n_runs
     p.elite_in = take_at(sizeof(gsgp_gen_stats) * G, i, "supplied survival decisions");
     p.code = take_at(4 * (m + r) * k, i, "genome codes");
     p.cval = take_at(8 * (m + r) * k, i, "genome constants");
-    p.ops = take_at(4 * (m + r) * k, i, "compiled ops");
-    p.opv = take_at(8 * (m + r) * k, i, "compiled constants");
+    p.ops = take_at(4 * ((m + r) * k + kOpPad), i, "compiled ops");
+    p.opv = take_at(8 * ((m + r) * k + kOpPad), i, "compiled constants");
     p.nops = take_at(4 * (m + r), i, "program lengths");
     p.need = take_at(4 * (m + r), i, "program stack needs");
     p.deep = take_at(4 * (m + r), i, "deep program list");
