@@ -346,42 +346,53 @@ __device__ __forceinline__ void eval_program(const int32_t* ops, const double* o
         }
       } else {
         // op(a, b): b is the top of the stack (or the fused terminal), a the
-        // value below it
-        double a[V], b[V];
-        if (cls == kClsStack) {
-#pragma unroll
-          for (int v = 0; v < V; ++v) {
-            a[v] = nos[v];
-            b[v] = tos[v];
-          }
-        } else {
-#pragma unroll
-          for (int v = 0; v < V; ++v) a[v] = tos[v];
-          if (cls == kClsFeature) {
-            feature(w, cv[u], b);
-          } else {
-#pragma unroll
-            for (int v = 0; v < V; ++v) b[v] = cv[u];
-          }
-        }
+        // value below it (or the top of the stack).  The two forms are
+        // separate call sites of `apply`, so neither first copies its
+        // operands into a common pair of registers.
         // Every operand is finite (finite features and constants, results
         // clamped here, protected division), so min/max clamp exactly as a
         // compare-and-select would.  The clamp sits in each branch, on the
         // arithmetic result itself, where the compiler knows the value needs
         // no NaN canonicalisation before min/max.
         auto clamp = [](double x) { return fmin(fmax(x, -kFltMax), kFltMax); };
-        if (fn == kFnAdd) {
+        auto apply = [&](const double (&a)[V], const double (&b)[V]) {
+          if (fn == kFnAdd) {
 #pragma unroll
-          for (int v = 0; v < V; ++v) tos[v] = clamp(a[v] + b[v]);
-        } else if (fn == kFnSub) {
+            for (int v = 0; v < V; ++v) tos[v] = clamp(a[v] + b[v]);
+          } else if (fn == kFnSub) {
 #pragma unroll
-          for (int v = 0; v < V; ++v) tos[v] = clamp(a[v] - b[v]);
-        } else if (fn == kFnMul) {
+            for (int v = 0; v < V; ++v) tos[v] = clamp(a[v] - b[v]);
+          } else if (fn == kFnMul) {
 #pragma unroll
-          for (int v = 0; v < V; ++v) tos[v] = clamp(a[v] * b[v]);
+            for (int v = 0; v < V; ++v) tos[v] = clamp(a[v] * b[v]);
+          } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+              // protected division without a per-lane branch: the quotient
+              // of a safe denominator is kept only where |b| >= 1e-6, and
+              // there it is a / b
+              const bool tiny = fabs(b[v]) < 1e-6;
+              const double q = a[v] / (tiny ? 1.0 : b[v]);
+              tos[v] = clamp(tiny ? 1.0 : q);
+            }
+          }
+        };
+        if (cls == kClsStack) {
+          double t0[V];
+#pragma unroll
+          for (int v = 0; v < V; ++v) t0[v] = tos[v];
+          apply(nos, t0);
         } else {
+          double x[V], t0[V];
 #pragma unroll
-          for (int v = 0; v < V; ++v) tos[v] = clamp((fabs(b[v]) < 1e-6) ? 1.0 : a[v] / b[v]);
+          for (int v = 0; v < V; ++v) t0[v] = tos[v];
+          if (cls == kClsFeature) {
+            feature(w, cv[u], x);
+          } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v) x[v] = cv[u];
+          }
+          apply(t0, x);
         }
         if (cls == kClsStack && d >= 3) {
 #pragma unroll
