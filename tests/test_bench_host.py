@@ -1,0 +1,100 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU guard, the algorithmic
+byte count of the variation kernel, the interpreter's gene-step count and
+the use of the committed counter summary.  Each count is checked against a
+plain per-item loop."""
+import os
+import re
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from oracle import oracle as orc  # noqa: E402
+from paper_2106_04034_amd import gsgp  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert res.returncode == 2
+    assert "one GPU" in res.stderr
+    assert res.stdout.strip() == ""
+
+
+def _records(rng, m, r, p_xo):
+    rec = np.zeros(m, dtype=gsgp.RECORD_DTYPE)
+    xo = rng.random(m) < p_xo
+    rec["op"] = xo.astype(np.int32)
+    rec["p1"] = rng.integers(0, m, m)
+    rec["p2"] = np.where(xo, rng.integers(0, m, m), -1)
+    rec["r1"] = rng.integers(0, r, m)
+    rec["r2"] = np.where(xo, -1, rng.integers(0, r, m))
+    return rec
+
+
+@pytest.mark.parametrize("p_xo", [0.0, 0.5, 1.0])
+def test_variation_bytes_count_each_distinct_row_once(p_xo):
+    rng = np.random.default_rng(3)
+    m, r, n_all, s, n_chunks = 200, 150, 1000, 4, 3
+    rec = _records(rng, m, r, p_xo)
+    parents, pool = set(), set()
+    for x in rec:
+        parents.add(int(x["p1"]))
+        if x["op"] == 1:
+            parents.add(int(x["p2"]))
+            pool.add(int(x["r1"]))
+        else:
+            pool.add(int(x["r1"]))
+            pool.add(int(x["r2"]))
+    assert bench.distinct_rows(rec) == (len(parents), len(pool))
+    want = s * n_all * (m + len(parents) + len(pool) + 1) + 8 * m * n_chunks + 32 * m
+    assert bench.vary_bytes(rec, n_all, s, m, n_chunks) == want
+
+
+def _steps_one(genome):
+    depth = ops = last = 0
+    for c in genome:
+        if c >= 0 or c == -5:
+            depth += 1
+            ops += 1
+        elif depth >= 2:
+            depth -= 1
+            ops += 1
+            last = ops
+    return last
+
+
+@pytest.mark.parametrize("k", [1, 7, 127])
+def test_gene_steps_count_pushes_and_valid_functions_up_to_the_last_function(k):
+    cfg = orc.Config(pop_size=40, pool_size=8, genome_len=k, seed=11)
+    codes, _ = orc.genomes(cfg, 5, orc.TAG_POPULATION, 40)
+    assert bench.gene_steps(codes) == sum(_steps_one(g) for g in codes)
+    # hand-made: "x0 x1 + c -" is 5 steps; a lone push and "x0" followed by
+    # functions on a one-value stack count nothing (no function runs)
+    hand = np.array([[0, 1, -1, -5, -2], [-1, -1, -1, -1, 0], [-1, 0, -1, -1, -1]], np.int32)
+    assert bench.gene_steps(hand) == 5
+
+
+def test_traffic_comes_from_the_counter_summary_only_for_the_same_kernel_sources(monkeypatch):
+    text = open(bench.PMC_SUMMARY).read()
+    digest = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text).group(1)
+    hbm = float(re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text).group(1))
+    monkeypatch.setattr(bench, "kernel_digest", lambda: digest)
+    assert bench.traffic_from_profile(1.0) == hbm
+    monkeypatch.setattr(bench, "kernel_digest", lambda: "0" * 16)
+    assert bench.traffic_from_profile(1.0) is None
+
+
+def test_kernel_digest_covers_the_kernels_and_their_shared_header(tmp_path, monkeypatch):
+    for name in ("kernels.hip", "common.hpp"):
+        (tmp_path / name).write_bytes(open(os.path.join(os.path.dirname(bench.KERNEL_SRC), name), "rb").read())
+    monkeypatch.setattr(bench, "KERNEL_SRC", str(tmp_path / "kernels.hip"))
+    d0 = bench.kernel_digest()
+    with open(tmp_path / "common.hpp", "ab") as f:
+        f.write(b"\n")
+    assert bench.kernel_digest() != d0
