@@ -156,7 +156,8 @@ gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_ru
  * -1 +, -2 -, -3 *, -4 protected /, -5 constant with its value in h_consts)
  * are given; both or neither.  Asynchronous apart from one small read-back.
  * Errors: GSGP_ERR_ARG (bad genome code), GSGP_ERR_STATE, GSGP_ERR_UNSUPPORTED
- * (stack deeper than 65 values), GSGP_ERR_HIP. */
+ * (a genome whose stack is deeper than 65 values before its last valid
+ * function; terminals after it never run and do not count), GSGP_ERR_HIP. */
 gsgp_status gsgp_eval_population(gsgp_handle* h, const int32_t* h_codes, const double* h_consts);
 
 /* Algorithm 1's loop body, n_gens times: variation draws (tournaments),

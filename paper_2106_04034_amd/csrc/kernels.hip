@@ -225,12 +225,15 @@ __global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs
   const double* cval = R.cval + (int64_t)prog * p.k;
   int32_t* ops = R.ops + (int64_t)prog * p.k;
   double* opv = R.opv + (int64_t)prog * p.k;
-  int depth = 0, n = 0, last = 0, deepest = 0;
+  // deepest: the deepest stack up to the last valid function; pushes after
+  // it are dropped and never run, so they do not count
+  int depth = 0, n = 0, last = 0, deepest = 0, peak = 0;
   int32_t prev = 0;  // the last op word written, ops[n - 1]
   for (int q = 0; q < p.k; ++q) {
     const int32_t c = code[q];
-    // depths beyond kMaxStack make the runtime reject the genomes before
-    // any interpretation; the cap only keeps the field inside its bits
+    // a depth beyond kMaxStack before the last function makes the runtime
+    // reject the genomes before any interpretation, and ops after the last
+    // function never run; the cap only keeps the field inside its bits
     const int dfield = (depth < kOpDepthMax ? depth : kOpDepthMax) << 4;
     if (c >= 0) {
       prev = (kClsPush << 2) | kPushFeature | dfield | (c << 16);
@@ -263,8 +266,9 @@ __global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs
       }
       --depth;
       last = n;
+      deepest = peak;
     }
-    deepest = depth > deepest ? depth : deepest;
+    peak = depth > peak ? depth : peak;
   }
   R.nops[prog] = last;
   const int need = deepest > 2 ? deepest - 2 : 0;  // the top two values live in registers

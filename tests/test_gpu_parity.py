@@ -172,6 +172,35 @@ def test_deep_programs_take_the_second_interpreter_pass():
     R.close()
 
 
+def test_terminals_after_the_last_function_do_not_count_towards_the_stack_limit():
+    """Only the stack up to a genome's last valid function limits what the
+    interpreter accepts: 100 terminals after it (or a genome of terminals
+    only) never run, so the population is accepted and its semantics equal
+    the oracle's (x0 + x1, and 0.0 where no function runs)."""
+    k, l, m, r = 128, 3, 4, 2
+    codes = np.full((m + r, k), -1, np.int32)
+    consts = np.zeros((m + r, k))
+    codes[0, 25:28] = [0, 1, -1]       # x0 x1 +, then 100 features
+    codes[0, 28:] = 2
+    codes[1, :] = 1                    # terminals only
+    codes[2, 25:28] = [2, -5, -3]      # x2 * c
+    consts[2, 26] = 0.75
+    codes[2, 28:] = 0
+    codes[3, 120:] = [0, 1, 2, -1, -2, 0, -3, -5]
+    consts[3, 127] = -2.0
+    codes[m:, :2] = [0, 1]             # pool: no function
+    assert _stack_depths(codes[:1]).max() == 101
+    d = dataset(90, 30, l, seed=51)
+    s = gsgp.Settings(pop_size=m, pool_size=r, genome_len=k, n_generations_max=1, seed=3)
+    R = _runner(s, [d])
+    R.eval_population(codes, consts)
+    X = np.concatenate([d.X_train, d.X_test])
+    want = orc.interpret(codes[:m], consts[:m], X)
+    assert np.array_equal(R.semantics(0, 0), want)
+    assert np.array_equal(want[0], X[:, 0] + X[:, 1]) and not want[1].any()
+    R.close()
+
+
 @pytest.mark.parametrize("n_train,n_test,l", [(1, 0, 1), (63, 1, 2), (513, 0, 3), (1500, 77, 4),
                                                (2048, 512, 7)])
 def test_ragged_and_edge_sizes(n_train, n_test, l):
