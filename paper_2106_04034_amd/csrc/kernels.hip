@@ -412,7 +412,13 @@ __device__ __forceinline__ void eval_program(const int32_t* ops, const double* o
 constexpr int kInterpV = 2;              // cases per lane
 constexpr int kInterpTile = kWave * kInterpV;  // cases per block
 static_assert(kInterpTile == kInterpCases, "the runtime plans kInterpCases-case blocks");
-constexpr int kInterpProgsPerWave = 8;   // programs each wave interprets on its case block
+// Programs each wave interprets on its case block.  One per wave keeps the
+// last waves of a launch from holding up its end when programs are long
+// (k = 2,047 at the Section 3.1 shape: 425 ms with one per wave, 449 with
+// four, 468 with eight; k = 127: 29.8 / 30.4 / 31.1 ms) and costs about 1 %
+// on 2,048 programs x 125,000 cases (4.1 against 4.0 ms).  Taking the
+// count as a launch argument instead of a constant cost 3 %.
+constexpr int kInterpProgsPerWave = 1;
 
 // ComputeSemantics(P) and ComputeSemantics(R) (Algorithm 1).  A block takes
 // one block of 128 cases of one run and a group of programs; each wave
