@@ -1210,6 +1210,8 @@ hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_
   const size_t shmem = (size_t)waves * slots * kInterpV * kWave * sizeof(double);
   const int progs = deep_max > 0 ? deep_max : p.m + p.r;
   const int32_t pgroups = (progs + waves * kInterpProgsPerWave - 1) / (waves * kInterpProgsPerWave);
+  // any workspace that fits on the device keeps this far below the limit
+  if (case_blocks * pgroups > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)(case_blocks * pgroups)), block(waves * kWave);
   const int deep_pass = deep_max > 0 ? 1 : 0;
   if (p.precision == GSGP_FP64)
