@@ -279,7 +279,8 @@ __global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs
 
 // Evaluate one compiled program on V cases per lane (Section 2.2
 // "Interpreter").  The op stream is wave-uniform and read with scalar loads,
-// eight ops per batch in one load of words and one of constants.  Stack element i of depth d (0 = bottom) lives in
+// eight ops per batch in one load of words and one of constants.  Stack
+// element i of depth d (0 = bottom) lives in
 // registers for the top two (tos = d-1, nos = d-2) and in LDS below them,
 // at stk[(i * V + v) * 64 + lane]; a function of the top two values reads
 // its new second operand from LDS only after it has produced its result, so
