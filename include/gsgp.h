@@ -300,8 +300,9 @@ gsgp_status gsgp_checkpoint_save(gsgp_handle* h, void* h_buf, size_t bytes);
  * itself is the caller's); the handle is then at the saved generation, as if
  * gsgp_eval_population and those generations had run.  A later
  * gsgp_eval_population restarts from generation 0.
- * Errors: GSGP_ERR_ARG (not a checkpoint, other configuration, truncated),
- * GSGP_ERR_STATE, GSGP_ERR_HIP. */
+ * Errors: GSGP_ERR_ARG (not a checkpoint, other configuration, truncated,
+ * or written by a version of the library with another compiled-genome
+ * format), GSGP_ERR_STATE, GSGP_ERR_HIP. */
 gsgp_status gsgp_checkpoint_load(gsgp_handle* h, const void* h_buf, size_t bytes);
 
 /* Byte offsets (within the workspace) of the guards that GSGP_FLAG_GUARDS
