@@ -69,6 +69,18 @@ def vary_bytes(rec: np.ndarray, n_all: int, s: int, m: int, n_chunks: int) -> in
 
 
 FP64_VALU_OPS = 78.6e12 / 2  # FP64 vector operations/s (the vendor FLOP/s counts an FMA as two)
+PROBE = os.path.join(ROOT, "paper_2106_04034_amd", "copy_probe")
+
+
+def streaming_probe(mode: str):
+    """GB/s of the streaming probe (1 GiB per array, 10 launches) on this
+    device, run as a child process; None when the probe is not built."""
+    if not os.path.exists(PROBE):
+        return None
+    import subprocess
+    res = subprocess.run([PROBE, str(1 << 30), "10", mode], capture_output=True, text=True, timeout=120)
+    m = re.search(r"GBps=([0-9.]+)", res.stdout)
+    return float(m.group(1)) if res.returncode == 0 and m else None
 
 
 def gene_steps(codes: np.ndarray) -> int:
@@ -222,6 +234,9 @@ def bench_single(args, wl, data, seed) -> dict:
     u = np.array([distinct_rows(rec[g]) for g in range(ng)])
     achieved = per_launch / (stages["vary_ms"] * 1e-3) / 1e9
     traffic = traffic_from_profile(per_launch) if wl.name == "single_fp32_100k" else None
+    # the 3 : 1 read / write streaming rate the same device reaches, as a
+    # practical ceiling next to the vendor peak
+    probes = {mode: streaming_probe(mode) for mode in ("mix31", "mix31nt")}
     codes, _ = R.genomes(0)
     interp = interpreter_rate(codes, n_all, eval_stages["compute_semantics_ms"])
     gen_rate = m * n_all / (stages["generation_ms"] * 1e-3)
@@ -267,7 +282,9 @@ def bench_single(args, wl, data, seed) -> dict:
                      "distinct_pool_rows": float(u[:, 1].mean()),
                      # what a kernel without cross-offspring reuse would move:
                      # three operand rows read and one written per offspring
-                     "operand_stream_GBps": 4 * s_bytes * m * n_all / (stages["vary_ms"] * 1e-3) / 1e9},
+                     "operand_stream_GBps": 4 * s_bytes * m * n_all / (stages["vary_ms"] * 1e-3) / 1e9,
+                     "probe_3to1_GBps": probes,
+                     "frac_of_probe": {k: achieved / v for k, v in probes.items() if v}},
         "interpreter": interp,
         "stages_ms": {k: round(v, 5) for k, v in stages.items()},
         "eval_population_ms": eval_ms,
