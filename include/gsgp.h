@@ -164,8 +164,9 @@ gsgp_status gsgp_eval_population(gsgp_handle* h, const int32_t* h_codes, const d
  * GSM/GSC on train and test semantics, ComputeFitness, survival with
  * elitism (Section 2.2).  h_stats (HOST, nullable) receives
  * [n_runs][n_gens] summaries and synchronises the stream.  Unless
- * GSGP_FLAG_NO_GRAPH is set the generation is captured once in a HIP graph
- * and replayed.
+ * GSGP_FLAG_NO_GRAPH is set, one generation and a block of 16 generations
+ * are each captured once in a HIP graph and replayed (16 at a time, then one
+ * at a time for the rest).
  * Errors: GSGP_ERR_ARG (n_gens < 1 or beyond n_generations_max),
  * GSGP_ERR_STATE (before gsgp_eval_population), GSGP_ERR_HIP. */
 gsgp_status gsgp_generation(gsgp_handle* h, int32_t n_gens, gsgp_gen_stats* h_stats);
