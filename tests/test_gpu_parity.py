@@ -253,18 +253,24 @@ def test_operator_variants(variant):
 
 
 def test_graph_and_no_graph_identical():
+    """37 generations in one call (two replays of the 16-generation graph,
+    then five of the one-generation graph), one generation per call, and
+    kernels launched one by one without graphs: the same bits."""
     d = dataset(900, 300, 6, seed=9)
+    G = 37
     out = []
-    for flags in (0, gsgp.FLAG_NO_GRAPH):
-        s = gsgp.Settings(pop_size=40, pool_size=20, n_generations_max=10, seed=3, flags=flags,
+    for flags, per_call in ((0, G), (0, 1), (gsgp.FLAG_NO_GRAPH, G)):
+        s = gsgp.Settings(pop_size=40, pool_size=20, n_generations_max=G, seed=3, flags=flags,
                           precision=gsgp.FP32_KAHAN)
         R = _runner(s, [d])
         R.eval_population()
-        R.generation(10, stats=False)
-        out.append((R.semantics(0, 0), R.fitness(0)[0], R.records(0, 1, 10), R.stats(0, 0, 11)))
+        for _ in range(G // per_call):
+            R.generation(per_call, stats=False)
+        out.append((R.semantics(0, 0), R.fitness(0)[0], R.records(0, 1, G), R.stats(0, 0, G + 1)))
         R.close()
-    for a, b in zip(out[0], out[1]):
-        assert np.array_equal(a, b)
+    for other in out[1:]:
+        for a, b in zip(out[0], other):
+            assert np.array_equal(a, b)
 
 
 def test_launch_shapes_do_not_change_bits():
