@@ -1009,27 +1009,36 @@ __global__ __launch_bounds__(256) void k_survive(const RunDev* __restrict__ runs
       const int64_t v1 = (v0 + per) < nvec ? (v0 + per) : nvec;
       const T* from = (const T*)R.S[cur];
       T* to = (T*)R.S[nxt];
-      // four vectors in flight per thread; all N cases of a vector lie in one chunk
+      // four vectors in flight per thread; all N cases of a vector lie in one chunk.
+      // With more than one wave, wave 0 takes the draws below while the
+      // other waves copy, so the copy's memory latency overlaps the draws.
       constexpr int U = 4;
-      const int64_t step = (int64_t)blockDim.x * U;
-      for (int64_t v = v0 + threadIdx.x; v < v1; v += step) {
-        VT buf[U];
-        int64_t at[U];
+      const bool split = blockDim.x > kWave;
+      const int ct = split ? (int)threadIdx.x - kWave : (int)threadIdx.x;
+      const int cn = split ? (int)blockDim.x - kWave : (int)blockDim.x;
+      const int64_t step = (int64_t)cn * U;
+      if (ct >= 0) {
+        for (int64_t v = v0 + ct; v < v1; v += step) {
+          VT buf[U];
+          int64_t at[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int64_t w = v + (int64_t)u * blockDim.x;
-          if (w < v1) {
-            const int64_t col = w * N;
-            buf[u] = *(const VT*)(from + tiled_index(R.tr_pad, R.te_pad, R.nch_tr, CH, m, src, col));
-            at[u] = tiled_index(R.tr_pad, R.te_pad, R.nch_tr, CH, m, dst, col);
+          for (int u = 0; u < U; ++u) {
+            const int64_t w = v + (int64_t)u * cn;
+            if (w < v1) {
+              const int64_t col = w * N;
+              buf[u] = *(const VT*)(from + tiled_index(R.tr_pad, R.te_pad, R.nch_tr, CH, m, src, col));
+              at[u] = tiled_index(R.tr_pad, R.te_pad, R.nch_tr, CH, m, dst, col);
+            }
           }
-        }
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-          if (v + (int64_t)u * blockDim.x < v1) *(VT*)(to + at[u]) = buf[u];
+          for (int u = 0; u < U; ++u)
+            if (v + (int64_t)u * cn < v1) *(VT*)(to + at[u]) = buf[u];
+        }
       }
     }
   }
+  // when the other waves copied the elite row, wave 0 alone takes the draws
+  const bool draw_split = copied && blockDim.x > kWave;
   // fitness of the individuals the next draw selects from
   auto view_new = [&](int i) { return (copied && i == dst) ? fP[src] : fO[i]; };
   auto view_cur = [&](int i) { return fP[i]; };
@@ -1062,7 +1071,8 @@ __global__ __launch_bounds__(256) void k_survive(const RunDev* __restrict__ runs
     const int i0 = per * bl;
     const int i1 = (i0 + per) < m ? (i0 + per) : m;
     gsgp_record* out = R.rec + (int64_t)(gen_draw - 1) * m;
-    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const int dn = draw_split ? kWave : (int)blockDim.x;  // threads taking draws
+    for (int i = i0 + (int)threadIdx.x; (int)threadIdx.x < dn && i < i1; i += dn) {
       out[i] = gen_mode ? draw_record(p, R.run_id, gen_draw, i, view_new)
                         : draw_record(p, R.run_id, gen_draw, i, view_cur);
     }
