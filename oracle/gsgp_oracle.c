@@ -30,8 +30,10 @@
  * (tests/golden/interpreter_programs.txt); random skip-free programs checked
  * against infix evaluation; sigmoid closed forms; RMSE against numpy; operator
  * identities and bounds; brute-force tournaments and rank frequencies;
- * elitism invariants; brute-force lineage reconstruction.  No function here
- * is "parity unpinned".
+ * elitism invariants; brute-force lineage reconstruction; least-squares
+ * scaling against hand-worked rows, numpy's least squares, exact linear
+ * targets and the optimality of the fit.  No function here is "parity
+ * unpinned".
  */
 #include <float.h>
 #include <math.h>
@@ -333,6 +335,60 @@ void orc_vary(const orc_record* rec, int32_t m, const double* S_P, const double*
       const double* rb = sigR + (int64_t)d->r2 * n;
       for (c = 0; c < n; ++c) o[c] = t[c] + d->ms * (ra[c] - rb[c]);
     }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Local search (the paper's Section 3.2 names GSGP with a local search
+ * method as the next step and Section 5 lists it as future work; neither
+ * defines it).  Reading: every offspring O formed by a variation operator is
+ * replaced by its least-squares linear scaling alpha + beta * O, with
+ * (alpha, beta) the simple linear regression of the training target t on O
+ * over the training cases.  The same (alpha, beta) scale the offspring's
+ * test cases.  With O = T + ms (R1 - R2) this is the regression-based local
+ * search of the mutation restricted to one coefficient on both mutation
+ * terms.  A (numerically) constant offspring has no regression slope: when
+ * sum (o - mean o)^2 <= 1e-10 * sum o^2 the offspring is kept unscaled
+ * (alpha = 0, beta = 1).
+ * Two-pass textbook form: means first, then centred sums. */
+void orc_ls_fit(const double* O, int32_t rows, int64_t n, const double* t, double* alpha, double* beta) {
+  int32_t i;
+#pragma omp parallel for schedule(static)
+  for (i = 0; i < rows; ++i) {
+    const double* o = O + (int64_t)i * n;
+    double so = 0.0, st = 0.0, soo = 0.0, sxx = 0.0, sxy = 0.0, mo, mt;
+    int64_t c;
+    for (c = 0; c < n; ++c) {
+      so += o[c];
+      st += t[c];
+      soo += o[c] * o[c];
+    }
+    mo = so / (double)n;
+    mt = st / (double)n;
+    for (c = 0; c < n; ++c) {
+      const double dx = o[c] - mo;
+      const double dy = t[c] - mt;
+      sxx += dx * dx;
+      sxy += dx * dy;
+    }
+    if (n > 0 && sxx > 1e-10 * soo) {
+      beta[i] = sxy / sxx;
+      alpha[i] = mt - beta[i] * mo;
+    } else {
+      alpha[i] = 0.0;
+      beta[i] = 1.0;
+    }
+  }
+}
+
+/* O[i][c] <- alpha[i] + beta[i] * O[i][c]. */
+void orc_ls_apply(double* O, int32_t rows, int64_t n, const double* alpha, const double* beta) {
+  int32_t i;
+#pragma omp parallel for schedule(static)
+  for (i = 0; i < rows; ++i) {
+    double* o = O + (int64_t)i * n;
+    int64_t c;
+    for (c = 0; c < n; ++c) o[c] = alpha[i] + beta[i] * o[c];
   }
 }
 

@@ -87,6 +87,8 @@ def lib():
         L.orc_survive.argtypes = [ctypes.c_int32, P, P, P, P, P, P, ctypes.c_int64, P, P,
                                   ctypes.c_int64, P, P]
         L.orc_survive.restype = ctypes.c_int32
+        L.orc_ls_fit.argtypes = [P, ctypes.c_int32, ctypes.c_int64, P, P, P]
+        L.orc_ls_apply.argtypes = [P, ctypes.c_int32, ctypes.c_int64, P, P]
         L.orc_set_threads.argtypes = [ctypes.c_int32]
         L.orc_max_threads.restype = ctypes.c_int32
         _lib = L
@@ -113,6 +115,7 @@ class Config:
     erc_hi: float = 1.0
     seed: int = 1
     run_id: int = 0
+    local_search: bool = False  # least-squares scaling of every offspring (see ls_fit)
 
     def c(self) -> _Cfg:
         return _Cfg(self.pop_size, self.pool_size, self.genome_len, self.tournament_size,
@@ -200,6 +203,30 @@ def vary(rec: np.ndarray, S_P: np.ndarray, sigR: np.ndarray) -> np.ndarray:
     return out
 
 
+def ls_fit(O: np.ndarray, t: np.ndarray):
+    """Least-squares scaling (alpha, beta) of each row of O against t
+    (local search; see orc_ls_fit for the reading)."""
+    O = np.ascontiguousarray(O, dtype=np.float64)
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    rows = O.shape[0]
+    n = O.shape[1] if O.ndim == 2 else 0
+    a = np.zeros(rows)
+    b = np.ones(rows)
+    if rows and n:
+        lib().orc_ls_fit(_p(O), rows, n, _p(t), _p(a), _p(b))
+    return a, b
+
+
+def ls_apply(O: np.ndarray, a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """alpha + beta * O row by row (a new array)."""
+    O = np.array(O, dtype=np.float64, order="C", copy=True)
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    if O.size:
+        lib().orc_ls_apply(_p(O), O.shape[0], O.shape[1], _p(a), _p(b))
+    return O
+
+
 def argmin(F: np.ndarray) -> int:
     F = np.ascontiguousarray(F, dtype=np.float64)
     return int(lib().orc_argmin(_p(F), F.size))
@@ -236,10 +263,12 @@ class Result:
     Ft: np.ndarray
     records: np.ndarray         # G x m raw variation draws
     elite: np.ndarray           # G x 3: (copied, src, dst)
+    scale: np.ndarray = None    # (G + 1) x m x 2: (alpha, beta) of each individual (local search)
     stats: list = field(default_factory=list)   # per generation 0..G: dict
     F_hist: list = field(default_factory=list)  # per generation 0..G: F copy
     Ft_hist: list = field(default_factory=list)
     S_hist: list = field(default_factory=list)  # per generation (train, test) when kept
+    replay: list = field(default_factory=list)  # per driven generation 1..G: replay check (see run)
 
 
 def initial_state(cfg: Config, Xtr, ytr, Xte, yte):
@@ -262,13 +291,65 @@ def _stats(F, Ft, copied, src, dst):
             "elite_copied": copied, "elite_src": src, "elite_dst": dst}
 
 
-def run(cfg: Config, Xtr, ytr, Xte, yte, G: int, drive=None, keep_semantics=False) -> Result:
+def _rel_gap(a: float, b: float) -> float:
+    return abs(a - b) / max(abs(a), abs(b), 1e-300)
+
+
+def replay_check(cfg: Config, gen: int, F: np.ndarray, rec: np.ndarray) -> dict:
+    """Checks one generation's given variation draws against the oracle's
+    own draws under its own fitness F (the fitness the tournaments of
+    generation ``gen`` select on).  Operator, pool rows and step do not
+    depend on fitness and must be equal; a tournament winner may differ only
+    where the candidates' fitness values nearly tie, so each disagreement is
+    counted with the relative fitness gap between the given winner and the
+    oracle's winner (0 for an exact tie)."""
+    own = select(cfg, gen, F)
+    draws = int(np.sum((own["op"] != rec["op"]) | (own["r1"] != rec["r1"]) | (own["r2"] != rec["r2"])
+                       | (own["ms"] != rec["ms"])))
+    gaps = []
+    for key in ("p1", "p2"):
+        valid = (own[key] >= 0) & (rec[key] >= 0)
+        diff = np.nonzero(valid & (own[key] != rec[key]))[0]
+        gaps += [_rel_gap(float(F[rec[key][i]]), float(F[own[key][i]])) for i in diff]
+    return {"draw_mismatch": draws, "winner_mismatch": len(gaps), "winner_gap_max": max(gaps, default=0.0)}
+
+
+def _elite_check(F, F_O, given) -> dict:
+    """The survival decision the oracle takes under its own fitness, against
+    a given one: equal, or differing only at a near tie (relative gap of the
+    comparison that decided it)."""
+    bP, bO = argmin(F), argmin(F_O)
+    copied = int(F[bP] < F_O[bO])
+    w = argmax(F_O)
+    own = (copied, bP if copied else -1, w if copied else -1)
+    given = tuple(int(v) for v in given)
+    if own == given:
+        return {"elite_mismatch": 0, "elite_gap": 0.0}
+    gaps = [_rel_gap(float(F[bP]), float(F_O[bO]))]
+    if given[0] and copied:
+        gaps += [_rel_gap(float(F[given[1]]), float(F[bP])), _rel_gap(float(F_O[given[2]]), float(F_O[w]))]
+    return {"elite_mismatch": 1, "elite_gap": max(gaps)}
+
+
+def run(cfg: Config, Xtr, ytr, Xte, yte, G: int, drive=None, keep_semantics=False,
+        on_generation=None) -> Result:
     """Algorithm 1 for G generations.
 
     ``drive`` (optional) is a pair (records G x m, elite G x 3) that replaces
-    the oracle's own draws and survival decisions; it is used to follow a
-    schedule that the oracle itself produced (e.g. to evaluate another
-    precision along the same lineage).
+    the oracle's own draws and survival decisions, to follow a lineage made
+    elsewhere (replay mode).  In replay mode every generation is also
+    checked against what the oracle would have decided itself (its own
+    Philox draws and tournaments under its own fitness, its own survival
+    decision): ``Result.replay[g - 1]`` holds the counts of disagreements and
+    the largest relative fitness gap behind one (see ``replay_check``).
+
+    With ``cfg.local_search`` every offspring formed by a variation operator
+    is replaced by its least-squares scaling before its fitness is taken
+    (``ls_fit``); the scaling of each individual is kept in
+    ``Result.scale``.
+
+    ``on_generation(g, S_tr, S_te, F, Ft)`` (optional) is called with the
+    population of generation g = 0..G after survival.
     """
     Xtr = np.ascontiguousarray(Xtr, dtype=np.float64)
     Xte = np.ascontiguousarray(Xte, dtype=np.float64).reshape(-1, Xtr.shape[1])
@@ -278,20 +359,38 @@ def run(cfg: Config, Xtr, ytr, Xte, yte, G: int, drive=None, keep_semantics=Fals
     m = cfg.pop_size
     records = np.zeros((G, m), dtype=RECORD_DTYPE)
     elite = np.zeros((G, 3), dtype=np.int32)
-    res = Result(code, cval, R_tr, R_te, S_tr, S_te, F, Ft, records, elite)
+    scale = np.zeros((G + 1, m, 2))
+    scale[0, :, 1] = 1.0
+    res = Result(code, cval, R_tr, R_te, S_tr, S_te, F, Ft, records, elite, scale)
     res.stats.append(_stats(F, Ft, 0, -1, -1))
     res.F_hist.append(F.copy())
     res.Ft_hist.append(Ft.copy())
     if keep_semantics:
         res.S_hist.append((S_tr.copy(), S_te.copy()))
+    if on_generation is not None:
+        on_generation(0, S_tr, S_te, F, Ft)
     for g in range(1, G + 1):
-        rec = drive[0][g - 1] if drive is not None else select(cfg, g, F)
+        if drive is not None:
+            rec = np.ascontiguousarray(drive[0][g - 1], dtype=RECORD_DTYPE)
+            check = replay_check(cfg, g, F, rec)
+        else:
+            rec = select(cfg, g, F)
         O_tr = vary(rec, S_tr, R_tr)
         O_te = vary(rec, S_te, R_te) if Xte.shape[0] else np.zeros((m, 0))
+        if cfg.local_search:
+            a, b = ls_fit(O_tr, ytr)
+            O_tr = ls_apply(O_tr, a, b)
+            if Xte.shape[0]:
+                O_te = ls_apply(O_te, a, b)
+            scale[g, :, 0], scale[g, :, 1] = a, b
+        else:
+            scale[g, :, 1] = 1.0
         F_O = rmse_rows(O_tr, ytr)
         Ft_O = rmse_rows(O_te, yte) if Xte.shape[0] else np.zeros(m)
         if drive is not None:
             copied, src, dst = (int(v) for v in drive[1][g - 1])
+            check.update(_elite_check(F, F_O, (copied, src, dst)))
+            res.replay.append(check)
             if copied:
                 O_tr[dst] = S_tr[src]
                 if Xte.shape[0]:
@@ -300,6 +399,8 @@ def run(cfg: Config, Xtr, ytr, Xte, yte, G: int, drive=None, keep_semantics=Fals
                 Ft_O[dst] = Ft[src]
         else:
             copied, src, dst = survive(F, Ft, F_O, Ft_O, S_tr, O_tr, S_te, O_te)
+        if copied:
+            scale[g, dst] = scale[g - 1, src]
         records[g - 1] = rec
         elite[g - 1] = (copied, src, dst)
         S_tr, S_te, F, Ft = O_tr, O_te, F_O, Ft_O
@@ -308,6 +409,8 @@ def run(cfg: Config, Xtr, ytr, Xte, yte, G: int, drive=None, keep_semantics=Fals
         res.Ft_hist.append(Ft.copy())
         if keep_semantics:
             res.S_hist.append((S_tr.copy(), S_te.copy()))
+        if on_generation is not None:
+            on_generation(g, S_tr, S_te, F, Ft)
     res.S_train, res.S_test, res.F, res.Ft = S_tr, S_te, F, Ft
     return res
 
@@ -362,6 +465,9 @@ def reconstruct(res: Result, cfg: Config, gen: int, individual: int, X: np.ndarr
                     vals[int(d["p2"])] * (1.0 - sig[int(d["r1"])])
             else:
                 nxt[i] = vals[int(d["p1"])] + float(d["ms"]) * (sig[int(d["r1"])] - sig[int(d["r2"])])
+            if cfg.local_search:
+                a, b = res.scale[g, i]
+                nxt[i] = a + b * nxt[i]
         vals = nxt
     return vals[individual]
 
@@ -370,14 +476,18 @@ def export_linear(res: Result, cfg: Config, gen: int, individual: int):
     """Compact model of a mutation-only lineage (the paper's own loop).
 
     Along a lineage of mutations only, individual ``individual`` of
-    generation ``gen`` is T(x) + sum_j w_j sigma(R_j(x)): one generation-0
-    population tree T and a weight per pool tree R_j, since every GSM step
-    adds ms (sigma(R_u) - sigma(R_v)) (Section 2, GSM; Section 2.1 stage 3,
-    lineage structures).  Returns (tree index, weights [r]); the weights are
-    accumulated forward, generation by generation (w[u] += ms, then
-    w[v] -= ms).  Raises ValueError if the lineage contains a crossover."""
-    m, r = cfg.pop_size, cfg.pool_size
-    muts = []
+    generation ``gen`` is c + b T(x) + sum_j w_j sigma(R_j(x)): one
+    generation-0 population tree T and a weight per pool tree R_j, since
+    every GSM step adds ms (sigma(R_u) - sigma(R_v)) (Section 2, GSM;
+    Section 2.1 stage 3, lineage structures).  Without local search c = 0 and
+    b = 1; with it each step is followed by the offspring's scaling
+    alpha + beta * (...), which scales c, b and w by beta and adds alpha to c.
+    Returns (tree index, c, b, weights [r]), accumulated forward generation by
+    generation: c = alpha + beta c, b = beta b, w = beta w, then
+    w[u] += beta ms, w[v] -= beta ms.  Raises ValueError if the lineage
+    contains a crossover."""
+    r = cfg.pool_size
+    steps = []
     i = individual
     for g in range(gen, 0, -1):
         copied, src, dst = (int(v) for v in res.elite[g - 1])
@@ -387,10 +497,15 @@ def export_linear(res: Result, cfg: Config, gen: int, individual: int):
         d = res.records[g - 1][i]
         if d["op"] == OP_XO:
             raise ValueError(f"the lineage contains a crossover at generation {g}")
-        muts.append(d)
+        steps.append((d, g, i))
         i = int(d["p1"])
     w = np.zeros(r)
-    for d in reversed(muts):
-        w[int(d["r1"])] += float(d["ms"])
-        w[int(d["r2"])] -= float(d["ms"])
-    return i, w
+    c, b = 0.0, 1.0
+    for d, g, j in reversed(steps):
+        alpha, beta = (float(res.scale[g, j, 0]), float(res.scale[g, j, 1])) if cfg.local_search else (0.0, 1.0)
+        c = alpha + beta * c
+        b = beta * b
+        w = beta * w
+        w[int(d["r1"])] += beta * float(d["ms"])
+        w[int(d["r2"])] -= beta * float(d["ms"])
+    return i, c, b, w

@@ -543,13 +543,14 @@ def test_export_linear_evaluates_to_the_lineage(orc):
     for X, want_of in ((Xtr, lambda i: res.S_train[i]), (Xnew, lambda i: orc.reconstruct(res, cfg, G, i, Xnew))):
         sig = orc.sigmoid(orc.interpret(res.code[m:], res.cval[m:], X))
         for i in range(m):
-            tree, w = orc.export_linear(res, cfg, G, i)
+            tree, c, b, w = orc.export_linear(res, cfg, G, i)
+            assert c == 0.0 and b == 1.0
             val = orc.interpret(res.code[tree:tree + 1], res.cval[tree:tree + 1], X)[0] + w @ sig
             want = want_of(i)
             assert np.allclose(val, want, rtol=1e-12, atol=1e-12 * np.max(np.abs(want)))
     # generation 0: the tree itself, no weights
-    tree, w = orc.export_linear(res, cfg, 0, 3)
-    assert tree == 3 and not w.any()
+    tree, c, b, w = orc.export_linear(res, cfg, 0, 3)
+    assert tree == 3 and not w.any() and (c, b) == (0.0, 1.0)
     cfg2 = orc.Config(pop_size=8, pool_size=6, seed=31)  # tournaments and crossover
     res2 = orc.run(cfg2, Xtr, ytr, Xte, yte, 6)
     with pytest.raises(ValueError):
@@ -602,3 +603,181 @@ def test_oracle_under_address_and_undefined_behaviour_sanitizers(tmp_path):
     out = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=120)
     assert out.returncode == 0, out.stderr[-2000:]
     assert "sanitized oracle ok" in out.stdout
+
+
+# --------------------------------------------------------------------------
+# Local search: least-squares scaling of each offspring (Section 3.2 and
+# Section 5 name GSGP with local search without defining it; the reading is
+# the simple linear regression of the training target on the offspring).
+
+def _ls_golden():
+    rows = []
+    for line in open(os.path.join(GOLDEN, "least_squares_worked.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = [part.split() for part in line.split("|")]
+        rows.append(([float(v) for v in f[0]], [float(v) for v in f[1]], float(f[2][0]), float(f[2][1]),
+                     float(f[3][0]), [float(v) for v in f[4]], [float(v) for v in f[5]], float(f[6][0])))
+    return rows
+
+
+def test_least_squares_hand_worked(orc):
+    for O, t, a, b, rmse, Ote, tte, rmse_te in _ls_golden():
+        ga, gb = orc.ls_fit(np.array([O]), np.array(t))
+        assert abs(ga[0] - a) <= 1e-12 * max(1.0, abs(a)) and abs(gb[0] - b) <= 1e-12 * max(1.0, abs(b)), (O, t)
+        Os = orc.ls_apply(np.array([O]), ga, gb)
+        assert abs(orc.rmse_rows(Os, np.array(t))[0] - rmse) <= 1e-12 * max(1.0, rmse)
+        Ot = orc.ls_apply(np.array([Ote]), ga, gb)
+        assert abs(orc.rmse_rows(Ot, np.array(tte))[0] - rmse_te) <= 1e-12 * max(1.0, rmse_te)
+
+
+def test_least_squares_matches_numpy_lstsq_and_is_optimal(orc):
+    rng = np.random.default_rng(41)
+    n = 300
+    O = rng.normal(0.3, 2.0, size=(12, n))
+    t = np.sin(rng.uniform(-2, 2, size=n)) + 0.1 * rng.normal(size=n)
+    a, b = orc.ls_fit(O, t)
+    Os = orc.ls_apply(O, a, b)
+    for i in range(O.shape[0]):
+        A = np.stack([np.ones(n), O[i]], axis=1)
+        coef = np.linalg.lstsq(A, t, rcond=None)[0]
+        assert np.allclose([a[i], b[i]], coef, rtol=1e-10, atol=1e-12)
+        base = float(np.sqrt(np.mean((Os[i] - t) ** 2)))
+        assert base <= float(np.sqrt(np.mean((O[i] - t) ** 2)))  # never worse than unscaled
+        for da, db in ((1e-3, 0), (-1e-3, 0), (0, 1e-3), (0, -1e-3)):
+            assert base <= float(np.sqrt(np.mean((a[i] + da + (b[i] + db) * O[i] - t) ** 2)))
+        r = t - Os[i]  # normal equations: residual orthogonal to 1 and to O
+        assert abs(r.sum()) <= 1e-10 * n and abs(r @ O[i]) <= 1e-10 * n * np.max(np.abs(O[i]))
+
+
+def test_least_squares_exact_cases(orc):
+    rng = np.random.default_rng(42)
+    O = rng.uniform(-3, 3, size=(4, 50))
+    # a target that already equals the offspring: nothing to scale
+    a, b = orc.ls_fit(O[:1], O[0])
+    assert a[0] == 0.0 and b[0] == 1.0
+    # an exactly linear target: recovered, zero error
+    t = -1.25 + 0.5 * O[1]
+    a, b = orc.ls_fit(O[1:2], t)
+    assert abs(a[0] + 1.25) <= 1e-12 and abs(b[0] - 0.5) <= 1e-12
+    assert orc.rmse_rows(orc.ls_apply(O[1:2], a, b), t)[0] <= 1e-13
+    # the scaled offspring does not depend on an affine change of O
+    a1, b1 = orc.ls_fit(O[2:3], O[3])
+    a2, b2 = orc.ls_fit(4.0 - 3.0 * O[2:3], O[3])
+    assert np.allclose(orc.ls_apply(O[2:3], a1, b1), orc.ls_apply(4.0 - 3.0 * O[2:3], a2, b2), atol=1e-12)
+    # a constant offspring is kept as it is
+    a, b = orc.ls_fit(np.full((1, 50), 0.7), O[3])
+    assert a[0] == 0.0 and b[0] == 1.0
+
+
+def test_run_with_local_search_scales_every_variation_offspring(orc):
+    """In a run with local search every offspring of a variation is the
+    least-squares scaling of the plain operator's output (the residual of
+    its training semantics sums to zero and is orthogonal to it), an elite
+    copy carries its source's values and scaling, and elitism still keeps
+    the best RMSE monotone."""
+    Xtr, ytr, Xte, yte = _small_data(n_tr=80, n_te=30, seed=11)
+    cfg = orc.Config(pop_size=24, pool_size=16, seed=7, local_search=True)
+    G = 10
+    res = orc.run(cfg, Xtr, ytr, Xte, yte, G, keep_semantics=True)
+    best = [s["best_train_rmse"] for s in res.stats]
+    assert all(b2 <= b1 for b1, b2 in zip(best, best[1:]))
+    m = cfg.pop_size
+    plain = orc.Config(pop_size=24, pool_size=16, seed=7)
+    for g in range(1, G + 1):
+        S_prev_tr, S_prev_te = res.S_hist[g - 1]
+        O_tr = orc.vary(res.records[g - 1], S_prev_tr, res.sigR_train)
+        O_te = orc.vary(res.records[g - 1], S_prev_te, res.sigR_test)
+        copied, src, dst = res.elite[g - 1]
+        S_tr, S_te = res.S_hist[g]
+        for i in range(m):
+            if copied and i == dst:
+                assert np.array_equal(S_tr[i], S_prev_tr[src])
+                assert np.array_equal(res.scale[g, i], res.scale[g - 1, src])
+                continue
+            a, b = res.scale[g, i]
+            assert np.allclose(S_tr[i], a + b * O_tr[i], rtol=0, atol=1e-12 * max(1.0, np.abs(S_tr[i]).max()))
+            assert np.allclose(S_te[i], a + b * O_te[i], rtol=0, atol=1e-12 * max(1.0, np.abs(S_te[i]).max()))
+            r = ytr - S_tr[i]
+            if b != 1.0 or a != 0.0:
+                assert abs(r.sum()) <= 1e-9 * len(r) and abs(r @ S_tr[i]) <= 1e-9 * len(r) * np.abs(S_tr[i]).max()
+        assert np.allclose(res.F_hist[g], np.sqrt(np.mean((S_tr - ytr) ** 2, axis=1)), rtol=1e-13)
+    # local search never makes the run's best worse than the plain run's after the same draws
+    assert res.scale[1:, :, 1].std() > 0
+    del plain
+
+
+def test_reconstruct_and_export_with_local_search(orc):
+    """Lineages of a run with local search: brute-force recursion (each step
+    followed by its offspring's recorded scaling) equals the stored
+    semantics and the memoised reconstruction on new cases; the compact model
+    c + b T + sum_j w_j sigma(R_j) of a mutation-only lineage evaluates to
+    the same values."""
+    Xtr, ytr, Xte, yte = _small_data(n_tr=9, n_te=4, seed=12)
+    cfg = orc.Config(pop_size=5, pool_size=4, seed=19, local_search=True)
+    G = 5
+    res = orc.run(cfg, Xtr, ytr, Xte, yte, G, keep_semantics=True)
+    m = cfg.pop_size
+
+    def R(j, X):
+        return orc.sigmoid(orc.interpret(res.code[m + j:m + j + 1], res.cval[m + j:m + j + 1], X))[0]
+
+    def brute(g, i, X):
+        if g == 0:
+            return orc.interpret(res.code[i:i + 1], res.cval[i:i + 1], X)[0]
+        copied, src, dst = res.elite[g - 1]
+        if copied and i == dst:
+            return brute(g - 1, int(src), X)
+        d = res.records[g - 1][i]
+        if d["op"] == orc.OP_XO:
+            o = brute(g - 1, int(d["p1"]), X) * R(int(d["r1"]), X) + \
+                brute(g - 1, int(d["p2"]), X) * (1.0 - R(int(d["r1"]), X))
+        else:
+            o = brute(g - 1, int(d["p1"]), X) + float(d["ms"]) * (R(int(d["r1"]), X) - R(int(d["r2"]), X))
+        a, b = res.scale[g, i]
+        return a + b * o
+
+    Xnew = np.random.default_rng(13).uniform(-1, 1, size=(6, Xtr.shape[1]))
+    for i in range(m):
+        assert np.array_equal(brute(G, i, Xtr), res.S_train[i])
+        assert np.array_equal(orc.reconstruct(res, cfg, G, i, Xnew), brute(G, i, Xnew))
+    cfgm = orc.Config(pop_size=6, pool_size=5, tournament_size=0, p_crossover=0.0, ms_random=1, seed=23,
+                      local_search=True)
+    resm = orc.run(cfgm, Xtr, ytr, Xte, yte, 8)
+    sig = orc.sigmoid(orc.interpret(resm.code[6:], resm.cval[6:], Xnew))
+    for i in range(6):
+        tree, c, b, w = orc.export_linear(resm, cfgm, 8, i)
+        val = c + b * orc.interpret(resm.code[tree:tree + 1], resm.cval[tree:tree + 1], Xnew)[0] + w @ sig
+        want = orc.reconstruct(resm, cfgm, 8, i, Xnew)
+        assert np.allclose(val, want, rtol=1e-12, atol=1e-12 * np.max(np.abs(want)))
+
+
+# --------------------------------------------------------------------------
+# Replay mode's own check (the oracle follows a given lineage and confirms
+# every recorded decision against its own draws and fitness)
+
+def test_replay_check_counts_disagreements_and_near_ties(orc):
+    Xtr, ytr, Xte, yte = _small_data(seed=14)
+    cfg = orc.Config(pop_size=32, pool_size=16, seed=29)
+    G = 8
+    a = orc.run(cfg, Xtr, ytr, Xte, yte, G)
+    b = orc.run(cfg, Xtr, ytr, Xte, yte, G, drive=(a.records, a.elite))
+    assert len(b.replay) == G
+    assert all(c["draw_mismatch"] == 0 and c["winner_mismatch"] == 0 and c["elite_mismatch"] == 0 for c in b.replay)
+    # a planted wrong tournament winner (not a near tie) is counted with its gap
+    rec = a.records.copy()
+    g, i = 3, int(np.nonzero(rec[3]["op"] == orc.OP_MUT)[0][0])
+    F2 = a.F_hist[g]
+    worst = int(np.argmax(F2))
+    assert rec[g][i]["p1"] != worst
+    rec[g][i]["p1"] = worst
+    c = orc.run(cfg, Xtr, ytr, Xte, yte, G, drive=(rec, a.elite))
+    assert c.replay[g]["winner_mismatch"] == 1 and c.replay[g]["winner_gap_max"] > 1e-3
+    assert sum(x["winner_mismatch"] for x in c.replay[:g]) == 0
+    # a planted pool row is a draw mismatch; a planted elite decision is counted
+    rec2 = a.records.copy()
+    rec2[1][0]["r1"] = (rec2[1][0]["r1"] + 1) % cfg.pool_size
+    el = a.elite.copy()
+    el[5] = (0, -1, -1) if el[5][0] else (1, 0, 1)
+    d = orc.run(cfg, Xtr, ytr, Xte, yte, G, drive=(rec2, el))
+    assert d.replay[1]["draw_mismatch"] == 1 and d.replay[5]["elite_mismatch"] == 1
