@@ -5,23 +5,30 @@ paper, arXiv 2106.04034): genome generation, interpretation of population and
 random-tree pool, initial fitness, then G generations of selection, GSM/GSC,
 fitness and survival.  Inputs are resident in HBM before timing starts.
 
-Default workload (single_fp32_100k): 100,000 train / 25,000 test cases,
-20 features U[-1, 1], sparse cubic target + N(0, 0.05), population 1,024,
-pool 1,024, 1,000 generations, FP32 semantics.  It prints one JSON line:
-offspring semantic elements/s (m * n_all * G per step), the roofline of the
-dominant kernel (variation + fitness partials) from HIP events on the library
-stream, and the CPU oracle's rate on a bounded sample.
+Default workload (batched_256): 256 independent runs of uneven size in one
+handle (n per run log-uniform in [200, 50,000], test n/4, 4..32 features
+U[-1, 1], sparse cubic target + N(0, 0.05); population 256, pool 256, 300
+generations, FP32 semantics with compensated fitness sums, 16 generations
+per HIP graph).  A step is one whole batched run of all 256.  It prints one
+JSON line: offspring semantic elements/s over all runs, the roofline of the
+variation kernel (one launch over all runs) from HIP events on the library
+stream, runs/hour against the plain per-run form (FP64, one handle per run,
+no graph) and a per-run FP32-Kahan form, the best-fitness error against an
+FP64 replay of every lineage and against the CPU oracle on four runs, and
+the CPU oracle's rate on a bounded sample of the runs.
 
 Other workloads (--workload) print their own line:
+  single_fp32_100k one run of 100,000 / 25,000 cases, m = r = 1,024, 1,000
+                   generations, FP32;
   large_fp32_1m    the same measurement on 1,000,000 / 250,000 cases, m = 2,048;
   plain_fp64_500x8 the same measurement on the small FP64 workload;
   precision_1m     FP32 and FP32-Kahan runs against an FP64 replay of the same
                    lineage: relative fitness drift per generation;
-  batched_256      256 uneven runs in one handle (FP32-Kahan, graph) against
-                   the plain per-run forms: runs/hour and fitness error;
   paper_shape_k127 / _k1023 / _k2047
                    the shape of the paper's speed-up study (Section 3.1): stage
                    times in its categories next to the single-thread oracle.
+--local-search turns on GSGP with local search (least-squares scaling of
+every offspring) for the single-run and batched workloads.
 """
 from __future__ import annotations
 
@@ -39,7 +46,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_vary_single_fp32_100k_pmc.md")
+BASELINE_METRIC = "offspring semantic elements/s + % HBM roofline; batched FP32 vs plain, 1e-4 fitness"
+# rocprofv3 counter summaries of the variation kernel, per workload
+PMC_SUMMARIES = {w: os.path.join(ROOT, "profiles", f"k_vary_{w}_pmc.md")
+                 for w in ("single_fp32_100k", "large_fp32_1m", "batched_256")}
 KERNEL_SRC = os.path.join(ROOT, "paper_2106_04034_amd", "csrc", "kernels.hip")
 
 
@@ -88,6 +98,11 @@ def gene_steps(codes: np.ndarray) -> int:
     pushes and valid functions up to its last valid function (the genes
     that shape its output; skipped functions and trailing pushes cost
     nothing once compiled).  Counted per case."""
+    return int(gene_steps_rows(codes).sum())
+
+
+def gene_steps_rows(codes: np.ndarray) -> np.ndarray:
+    """gene_steps of each genome row."""
     depth = np.zeros(codes.shape[0], np.int64)
     ops = np.zeros(codes.shape[0], np.int64)
     last = np.zeros(codes.shape[0], np.int64)
@@ -98,11 +113,17 @@ def gene_steps(codes: np.ndarray) -> int:
         ops += push | fn
         depth += push.astype(np.int64) - fn.astype(np.int64)
         last = np.where(fn, ops, last)
-    return int(last.sum())
+    return last
 
 
 def interpreter_rate(codes: np.ndarray, n_cases: int, ms: float) -> dict:
-    steps = gene_steps(codes) * n_cases
+    return interpreter_rate_rows(codes, np.full(codes.shape[0], n_cases), ms)
+
+
+def interpreter_rate_rows(codes: np.ndarray, n_cases: np.ndarray, ms: float) -> dict:
+    """Gene-steps/s of ComputeSemantics when genome row j runs on n_cases[j]
+    cases (runs of uneven size in one handle)."""
+    steps = int(np.sum(gene_steps_rows(codes) * np.asarray(n_cases, np.int64)))
     rate = steps / (ms * 1e-3)
     return {"bound": "alu", "gene_steps": steps, "gene_steps_per_s": rate, "peak_fp64_ops_per_s": FP64_VALU_OPS,
             "frac": rate / FP64_VALU_OPS, "compute_semantics_ms": ms,
@@ -111,12 +132,12 @@ def interpreter_rate(codes: np.ndarray, n_cases: int, ms: float) -> dict:
                     "the clamp) plus the interpretive dispatch"}
 
 
-def traffic_from_profile(per_launch_alg: float):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source; None otherwise."""
-    if not os.path.exists(PMC_SUMMARY):
+def traffic_from_profile(path: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; None otherwise."""
+    if not os.path.exists(path):
         return None
-    text = open(PMC_SUMMARY).read()
+    text = open(path).read()
     m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
     t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
     if not m or not t or m.group(1) != kernel_digest():
@@ -134,7 +155,8 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(workload, data, G: int, seed: int, frac: int = 4, g_sample: int = 30, threads: int = 0):
+def cpu_baseline(workload, data, G: int, seed: int, frac: int = 4, g_sample: int = 30, threads: int = 0,
+                 local_search: bool = False):
     """The FP64 CPU oracle on a case slice of the same workload (all of m, r,
     k; 1/frac of the train and test cases), timed for initialisation and
     g_sample generations on `threads` host cores (0: every core), then
@@ -148,7 +170,7 @@ def cpu_baseline(workload, data, G: int, seed: int, frac: int = 4, g_sample: int
     Xtr, ytr = data.X_train[:ntr], data.y_train[:ntr]
     Xte, yte = data.X_test[:nte], data.y_test[:nte]
     cfg = orc.Config(pop_size=workload.pop_size, pool_size=workload.pool_size,
-                     genome_len=workload.genome_len, seed=seed)
+                     genome_len=workload.genome_len, seed=seed, local_search=local_search)
     t0 = time.perf_counter()
     state = orc.initial_state(cfg, Xtr, ytr, Xte, yte)
     t1 = time.perf_counter()
@@ -156,6 +178,9 @@ def cpu_baseline(workload, data, G: int, seed: int, frac: int = 4, g_sample: int
     for g in range(1, g_sample + 1):
         rec = orc.select(cfg, g, F)
         O_tr, O_te = orc.vary(rec, S_tr, R_tr), orc.vary(rec, S_te, R_te)
+        if local_search:
+            a, b = orc.ls_fit(O_tr, ytr)
+            O_tr, O_te = orc.ls_apply(O_tr, a, b), orc.ls_apply(O_te, a, b)
         F_O, Ft_O = orc.rmse_rows(O_tr, ytr), orc.rmse_rows(O_te, yte)
         orc.survive(F, Ft, F_O, Ft_O, S_tr, O_tr, S_te, O_te)
         S_tr, S_te, F, Ft = O_tr, O_te, F_O, Ft_O
@@ -186,7 +211,8 @@ def bench_single(args, wl, data, seed) -> dict:
 
     G = args.generations or wl.generations
     prec = gsgp.PRECISIONS[wl.precision]
-    R = gsgp.Runner(settings_for(gsgp, wl, G, prec, seed), [data], stream=torch.cuda.Stream())
+    flags = gsgp.FLAG_LOCAL_SEARCH if args.local_search else 0
+    R = gsgp.Runner(settings_for(gsgp, wl, G, prec, seed, flags), [data], stream=torch.cuda.Stream())
     n_all = data.X_train.shape[0] + data.X_test.shape[0]
     m = wl.pop_size
     s_bytes = 8 if prec == gsgp.FP64 else 4
@@ -233,7 +259,8 @@ def bench_single(args, wl, data, seed) -> dict:
     per_launch = float(np.mean([vary_bytes(rec[g], n_all, s_bytes, m, n_chunks) for g in range(ng)]))
     u = np.array([distinct_rows(rec[g]) for g in range(ng)])
     achieved = per_launch / (stages["vary_ms"] * 1e-3) / 1e9
-    traffic = traffic_from_profile(per_launch) if wl.name == "single_fp32_100k" else None
+    traffic = traffic_from_profile(PMC_SUMMARIES[wl.name]) if wl.name in PMC_SUMMARIES and not args.local_search \
+        else None
     # the 3 : 1 read / write streaming rate the same device reaches, as a
     # practical ceiling next to the vendor peak
     probes = {mode: streaming_probe(mode) for mode in ("mix31", "mix31nt")}
@@ -273,7 +300,7 @@ def bench_single(args, wl, data, seed) -> dict:
                    "n_features": data.X_train.shape[1], "pop_size": m, "pool_size": wl.pool_size,
                    "genome_len": wl.genome_len, "generations": G, "tournament_size": wl.tournament_size,
                    "p_crossover": wl.p_crossover, "mutation_step": wl.mutation_step,
-                   "precision": wl.precision, "launch": tuned},
+                   "precision": wl.precision, "local_search": bool(args.local_search), "launch": tuned},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_vary (GSM/GSC + chunk partial sums)",
@@ -299,13 +326,14 @@ def bench_single(args, wl, data, seed) -> dict:
         frac = 4 if n_all <= 200_000 else 32
         if n_all < 10_000:
             frac = 1
-        cb = cpu_baseline(wl, data, G, seed, frac=frac)
+        cb = cpu_baseline(wl, data, G, seed, frac=frac, local_search=args.local_search)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         out["cpu_baseline"]["gen_elements_per_s"] = cb["gen_elements_per_s"]
         out["cpu_baseline"]["cpu_model"] = cpu_model()
         # the sequential reference point (the paper compares with a sequential
         # CPU implementation): one thread on a smaller slice
-        c1 = cpu_baseline(wl, data, G, seed, frac=frac * 4 if frac > 1 else 1, g_sample=10, threads=1)
+        c1 = cpu_baseline(wl, data, G, seed, frac=frac * 4 if frac > 1 else 1, g_sample=10, threads=1,
+                          local_search=args.local_search)
         out["cpu_baseline"]["one_thread"] = {k: c1[k] for k in ("value", "gen_elements_per_s", "sample")}
     return out
 
@@ -368,11 +396,89 @@ def bench_precision(args) -> dict:
             "forms": report, "end_of_run_within_1e-4": ok}
 
 
+def _n_chunks(n_tr: int, n_te: int, s_bytes: int) -> int:
+    chunk = 4096 // s_bytes  # canonical chunk: 4 KiB of a semantic row
+    return -(-(-(-n_tr // 64) * 64) // chunk) + -(-(-(-n_te // 64) * 64) // chunk)
+
+
+def cpu_baseline_runs(wl, datasets, G: int, seed: int, pick, g_sample: int, threads: int = 0,
+                      local_search: bool = False):
+    """The FP64 CPU oracle on a fixed subset of the independent runs (every
+    case of each picked run; initialisation and g_sample generations), on
+    `threads` host cores (0: every core), scaled to all runs and G
+    generations by the runs' offspring elements per generation."""
+    from oracle import oracle as orc
+    all_cores = len(os.sched_getaffinity(0))
+    cores = threads or all_cores
+    orc.set_threads(cores)
+    t_init = t_gen = 0.0
+    elems_pick = 0
+    for j in pick:
+        d = datasets[j]
+        cfg = orc.Config(pop_size=wl.pop_size, pool_size=wl.pool_size, genome_len=wl.genome_len,
+                         seed=seed, run_id=j, local_search=local_search)
+        t0 = time.perf_counter()
+        _, _, S_tr, S_te, R_tr, R_te, F, Ft = orc.initial_state(cfg, d.X_train, d.y_train, d.X_test, d.y_test)
+        t1 = time.perf_counter()
+        for g in range(1, g_sample + 1):
+            rec = orc.select(cfg, g, F)
+            O_tr, O_te = orc.vary(rec, S_tr, R_tr), orc.vary(rec, S_te, R_te)
+            if local_search:
+                a, b = orc.ls_fit(O_tr, d.y_train)
+                O_tr, O_te = orc.ls_apply(O_tr, a, b), orc.ls_apply(O_te, a, b)
+            F_O, Ft_O = orc.rmse_rows(O_tr, d.y_train), orc.rmse_rows(O_te, d.y_test)
+            orc.survive(F, Ft, F_O, Ft_O, S_tr, O_tr, S_te, O_te)
+            S_tr, S_te, F, Ft = O_tr, O_te, F_O, Ft_O
+        t2 = time.perf_counter()
+        t_init += t1 - t0
+        t_gen += (t2 - t1) / g_sample
+        elems_pick += wl.pop_size * (d.X_train.shape[0] + d.X_test.shape[0])
+    orc.set_threads(all_cores)
+    elems_all = sum(wl.pop_size * (d.X_train.shape[0] + d.X_test.shape[0]) for d in datasets)
+    scale = elems_all / elems_pick
+    t_step = scale * (t_init + t_gen * G)
+    sample = (f"FP64 oracle, {cores} threads: {len(pick)} of the {len(datasets)} runs (every case), "
+              f"m=r={wl.pop_size}, init {t_init:.2f} s + {g_sample} generations {t_gen * g_sample:.2f} s, "
+              f"scaled by offspring elements to all runs and init + {G} generations")
+    return {"value": elems_all * G / t_step, "unit": "offspring elements/s", "cores": cores, "kind": "oracle",
+            "sample": sample, "runs_per_hour": len(datasets) * 3600 / t_step,
+            "gen_elements_per_s": elems_pick / t_gen}
+
+
+def oracle_fitness_check(wl, datasets, G, seed, rec, elite, F_dev, picks, local_search=False):
+    """The oracle follows the device lineage of the picked runs (replay mode,
+    every case, FP64) for G generations; returns the relative error of the
+    device's final fitness at the oracle's best index, the largest over the
+    population, and the replay check's near-tie counts."""
+    from oracle import oracle as orc
+    worst_best = worst_all = 0.0
+    ties = 0
+    for j in picks:
+        d = datasets[j]
+        cfg = orc.Config(pop_size=wl.pop_size, pool_size=wl.pool_size, genome_len=wl.genome_len,
+                         seed=seed, run_id=j, local_search=local_search)
+        orec = np.zeros(rec[j].shape, dtype=orc.RECORD_DTYPE)
+        for f in ("op", "p1", "p2", "r1", "r2", "ms"):
+            orec[f] = rec[j][f]
+        el = np.stack([elite[j]["elite_copied"], elite[j]["elite_src"], elite[j]["elite_dst"]], axis=1)
+        res = orc.run(cfg, d.X_train, d.y_train, d.X_test, d.y_test, G, drive=(orec, el))
+        b = int(np.argmin(res.F))
+        worst_best = max(worst_best, abs(F_dev[j][b] - res.F[b]) / res.F[b])
+        worst_all = max(worst_all, float(np.max(np.abs(F_dev[j] - res.F) / res.F)))
+        ties += sum(c["winner_mismatch"] + c["elite_mismatch"] for c in res.replay)
+    return {"runs": [int(j) for j in picks], "best_rel_err_max": worst_best, "population_rel_err_max": worst_all,
+            "near_tie_disagreements": ties}
+
+
 def bench_batched(args) -> dict:
-    """256 uneven runs: one batched FP32-Kahan handle (HIP graph) against the
-    plain per-run form (one FP64 handle per run, launches one by one) and a
-    per-run FP32-Kahan form; whole runs timed, set-up excluded.  Fitness error
-    of the batched runs against an FP64 replay of their own lineages."""
+    """The metric's own comparison: 256 uneven runs in one batched
+    FP32-Kahan handle (every stage one launch over all runs, 16 generations
+    per HIP graph) against the plain per-run form (one FP64 handle per run,
+    launches one by one, no graph) and a per-run FP32-Kahan form.  A step is
+    one whole batched run: initialisation of every run and G generations.
+    The fitness error of the batched runs is measured against an FP64 replay
+    of their own lineages on the GPU (every run) and against the CPU oracle
+    following the same lineages (four runs)."""
     import torch
     from paper_2106_04034_amd import gsgp, synth
 
@@ -382,9 +488,10 @@ def bench_batched(args) -> dict:
     datasets = synth.batched_runs(n_runs)
     seed = synth.evolution_seed(4)
     stream = torch.cuda.Stream()
-    out = {}
+    flags = gsgp.FLAG_LOCAL_SEARCH if args.local_search else 0
+    n_all = sum(d.X_train.shape[0] + d.X_test.shape[0] for d in datasets)
 
-    B = gsgp.Runner(settings_for(gsgp, wl, G, gsgp.FP32_KAHAN, seed), datasets, stream=stream)
+    B = gsgp.Runner(settings_for(gsgp, wl, G, gsgp.FP32_KAHAN, seed, flags), datasets, stream=stream)
     B.eval_population()
     if args.launch:
         w, o, x, g = (int(v) for v in args.launch.split(","))
@@ -392,44 +499,57 @@ def bench_batched(args) -> dict:
         tuned = {"waves": w, "offspring_per_block": o, "xcd_remap": x, "max_blocks": g}
     else:
         tuned = None if args.no_autotune else B.autotune()
-    B.generation(min(G, 3), stats=False)  # warm up graph capture
+
+    def step():
+        B.eval_population()
+        B.generation(G, stats=False)
+
+    for _ in range(args.warmup):
+        step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    B.eval_population()
-    B.generation(G, stats=False)
+    for _ in range(args.steps):
+        step()
     torch.cuda.synchronize()
-    t_batched = time.perf_counter() - t0
-    rec = np.stack([B.records(j, 1, G) for j in range(n_runs)])
-    elite = np.stack([B.stats(j, 1, G) for j in range(n_runs)])
+    t_step = (time.perf_counter() - t0) / args.steps
+    value = wl.pop_size * n_all * G / t_step
+    rec = [B.records(j, 1, G) for j in range(n_runs)]
+    elite = [B.stats(j, 1, G) for j in range(n_runs)]
     final = np.stack([B.stats(j, G, 1)[0] for j in range(n_runs)])
     F_b = np.stack([B.fitness(j)[0] for j in range(n_runs)])
     # roofline of the batched variation launch: algorithmic bytes of every
-    # run (distinct parent / pool rows from its records) over the launch time
+    # run (distinct parent / pool rows from its records) over its launch
+    # time from HIP events on the library stream
     B.eval_population()
-    ng = min(G, 20)
+    ng = min(G, args.stage_gens)
     stg = B.time_stages(ng)
-    chunk = 4096 // 4
     alg = 0.0
     for j, d in enumerate(datasets):
         n_tr, n_te = d.X_train.shape[0], d.X_test.shape[0]
-        n_chunks = -(-(-(-n_tr // 64) * 64) // chunk) + -(-(-(-n_te // 64) * 64) // chunk)
         rj = B.records(j, 1, ng)
-        alg += float(np.mean([vary_bytes(rj[g], n_tr + n_te, 4, wl.pop_size, n_chunks) for g in range(ng)]))
+        alg += float(np.mean([vary_bytes(rj[g], n_tr + n_te, 4, wl.pop_size, _n_chunks(n_tr, n_te, 4))
+                              for g in range(ng)]))
+    eval_stages = B.time_eval()
+    codes = np.concatenate([B.genomes(j)[0] for j in range(n_runs)])
+    n_cases = np.repeat([d.X_train.shape[0] + d.X_test.shape[0] for d in datasets], wl.pop_size + wl.pool_size)
     B.close()
     achieved = alg / (stg["vary_ms"] * 1e-3) / 1e9
+    probes = {mode: streaming_probe(mode) for mode in ("mix31", "mix31nt")}
 
-    R64 = gsgp.Runner(settings_for(gsgp, wl, G, gsgp.FP64, seed), datasets, stream=stream)
+    # FP64 replay of every run's lineage on the GPU
+    R64 = gsgp.Runner(settings_for(gsgp, wl, G, gsgp.FP64, seed, flags), datasets, stream=stream)
     R64.eval_population()
-    R64.replay(rec, elite, stats=False)
+    R64.replay(np.stack(rec), np.stack(elite), stats=False)
     F_64 = np.stack([R64.fitness(j)[0] for j in range(n_runs)])
     R64.close()
     idx = final["best_index"]
     err = np.abs(F_b[np.arange(n_runs), idx] - F_64[np.arange(n_runs), idx]) / F_64[np.arange(n_runs), idx]
 
-    def per_run(precision, flags):
+    def per_run(precision, run_flags):
         total = 0.0
         for j, d in enumerate(datasets):
-            R = gsgp.Runner(settings_for(gsgp, wl, G, precision, seed + j, flags), [d], stream=stream)
+            # run j of the batch: the same key word 1 (run index) as inside the batch
+            R = gsgp.Runner(settings_for(gsgp, wl, G, precision, seed, run_flags | flags), [d], stream=stream)
             torch.cuda.synchronize()
             t = time.perf_counter()
             R.eval_population()
@@ -444,22 +564,58 @@ def bench_batched(args) -> dict:
     else:
         t_plain = per_run(gsgp.FP64, gsgp.FLAG_NO_GRAPH)
         t_single32 = per_run(gsgp.FP32_KAHAN, 0)
-    n_all = sum(d.X_train.shape[0] + d.X_test.shape[0] for d in datasets)
-    return {"metric": "runs/hour, batched FP32-Kahan vs plain per-run", "value": n_runs * 3600 / t_batched,
-            "unit": "runs/hour", "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
-            "config": {"workload": wl.name, "runs": n_runs, "total_cases": n_all, "pop_size": wl.pop_size,
-                       "pool_size": wl.pool_size, "generations": G, "launch": tuned},
-            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "kernel": "k_vary over all runs (one launch)",
-                         "alg_bytes_per_launch": alg, "launch_ms": stg["vary_ms"]},
-            "stages_ms": {k: round(v, 5) for k, v in stg.items()},
-            "batched_fp32_kahan_graph": {"runs_per_hour": n_runs * 3600 / t_batched, "seconds": t_batched,
-                                         "offspring_elements_per_s": wl.pop_size * n_all * G / t_batched},
-            "plain_per_run_fp64": {"runs_per_hour": n_runs * 3600 / t_plain, "seconds": t_plain},
-            "per_run_fp32_kahan_graph": {"runs_per_hour": n_runs * 3600 / t_single32, "seconds": t_single32},
-            "speedup_vs_plain": t_plain / t_batched,
-            "best_fitness_rel_err_vs_fp64_replay": {"max": float(err.max()), "median": float(np.median(err))},
-            "within_1e-4": bool(err.max() <= 1e-4)}
+    per_launch_traffic = traffic_from_profile(PMC_SUMMARIES["batched_256"]) if not args.local_search else None
+    out = {
+        "metric": BASELINE_METRIC,
+        "value": value,
+        "unit": "offspring elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "runs": n_runs, "total_cases": n_all, "pop_size": wl.pop_size,
+                   "pool_size": wl.pool_size, "genome_len": wl.genome_len, "generations": G,
+                   "tournament_size": wl.tournament_size, "p_crossover": wl.p_crossover,
+                   "mutation_step": wl.mutation_step, "precision": "fp32_kahan", "graph_generations": 16,
+                   "local_search": bool(args.local_search), "launch": tuned},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": per_launch_traffic,
+                     "kernel": "k_vary over all 256 runs (one launch)",
+                     "alg_bytes_per_launch": alg, "launch_ms": stg["vary_ms"],
+                     "probe_3to1_GBps": probes,
+                     "frac_of_probe": {k: achieved / v for k, v in probes.items() if v}},
+        "stages_ms": {k: round(v, 5) for k, v in stg.items()},
+        "eval_stages_ms": {k: round(v, 5) for k, v in eval_stages.items()},
+        "interpreter": interpreter_rate_rows(codes, n_cases, eval_stages["compute_semantics_ms"]),
+        "runs_per_hour": {"batched_fp32_kahan_graph": n_runs * 3600 / t_step,
+                          "plain_per_run_fp64_no_graph": n_runs * 3600 / t_plain,
+                          "per_run_fp32_kahan_graph": n_runs * 3600 / t_single32},
+        "seconds_for_all_runs": {"batched_fp32_kahan_graph": t_step, "plain_per_run_fp64_no_graph": t_plain,
+                                 "per_run_fp32_kahan_graph": t_single32},
+        "speedup_vs_plain": t_plain / t_step,
+        "best_fitness_rel_err_vs_fp64_replay": {"max": float(err.max()), "median": float(np.median(err))},
+        "within_1e-4": bool(err.max() <= 1e-4),
+    }
+    if not args.no_cpu_baseline:
+        sizes = np.array([d.X_train.shape[0] for d in datasets])
+        order = np.argsort(sizes)
+        picks = [int(order[0]), int(order[len(order) // 3]), int(order[2 * len(order) // 3]), int(order[-1])]
+        out["oracle_fitness_check"] = oracle_fitness_check(wl, datasets, G, seed, rec, elite, F_b, picks,
+                                                           args.local_search)
+        cb = cpu_baseline_runs(wl, datasets, G, seed, list(range(0, n_runs, 4)), 50,
+                               local_search=args.local_search)
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        out["cpu_baseline"]["runs_per_hour"] = cb["runs_per_hour"]
+        out["cpu_baseline"]["cpu_model"] = cpu_model()
+        c1 = cpu_baseline_runs(wl, datasets, G, seed, list(range(0, n_runs, 32)), 10, threads=1,
+                               local_search=args.local_search)
+        out["cpu_baseline"]["one_thread"] = {k: c1[k] for k in ("value", "runs_per_hour", "sample")}
+    return out
 
 
 def bench_paper_shape(args, wl) -> dict:
@@ -570,7 +726,9 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="single_fp32_100k")
+    ap.add_argument("--workload", default="batched_256")
+    ap.add_argument("--local-search", action="store_true",
+                    help="GSGP with local search (single-run and batched workloads)")
     ap.add_argument("--stage-gens", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -584,9 +742,9 @@ def main() -> int:
                          "(skips autotuning)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              "(a single run shards over fitness cases only in design, see the design notes)",
-              file=sys.stderr)
+        print(f"bench.py: measures one GPU only; --gpus {args.gpus} is not supported (independent runs "
+              "would shard over GPUs with no communication and a single run over its fitness cases, "
+              "neither of which is built here)", file=sys.stderr)
         return 2
 
     from paper_2106_04034_amd import synth

@@ -65,6 +65,16 @@ typedef enum { GSGP_FP64 = 0, GSGP_FP32 = 1, GSGP_FP32_KAHAN = 2 } gsgp_precisio
                                   buffer (gsgp_workspace_size grows accordingly), checked
                                   after every call that launches kernels; an overwritten
                                   guard poisons the handle (GSGP_ERR_STATE) */
+#define GSGP_FLAG_LOCAL_SEARCH 4u /* GSGP with local search (named in Sections 3.2 and 5 of
+                                  the paper, not defined there): every offspring O of a
+                                  variation operator becomes alpha + beta * O, with
+                                  (alpha, beta) the least-squares fit of the training
+                                  target on O over the training cases; the same scaling
+                                  applies to the offspring's test cases.  A numerically
+                                  constant offspring (sum (o - mean o)^2 <= 1e-10 *
+                                  sum o^2) is kept (alpha = 0, beta = 1).  The scaling
+                                  of every individual is kept (gsgp_get_scaling) and
+                                  followed by reconstruction and export. */
 
 /* Run parameters: the inputs of Algorithm 1 plus operator settings.
  * Defaults used by the project's workloads are given in brackets. */
@@ -154,10 +164,15 @@ gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_ru
  * Genomes are drawn from Philox unless h_codes/h_consts (HOST arrays,
  * [n_runs][m + r][k], population rows then pool rows; code >= 0 is a feature,
  * -1 +, -2 -, -3 *, -4 protected /, -5 constant with its value in h_consts)
- * are given; both or neither.  Asynchronous apart from one small read-back.
- * Errors: GSGP_ERR_ARG (bad genome code), GSGP_ERR_STATE, GSGP_ERR_UNSUPPORTED
- * (a genome whose stack is deeper than 65 values before its last valid
- * function; terminals after it never run and do not count), GSGP_ERR_HIP. */
+ * are given; both or neither.  Every genome is accepted: stacks that do not
+ * fit a wavefront's LDS column are kept in the workspace's spill stacks
+ * (sized by gsgp_workspace_size for genome_len), so no population is refused
+ * once the arguments are valid.  Arguments (genome codes in range, finite
+ * constants) are checked on the host before any device work, so a rejected
+ * call leaves the current run untouched.  Asynchronous apart from one small
+ * read-back.
+ * Errors: GSGP_ERR_ARG (bad genome code or constant), GSGP_ERR_STATE,
+ * GSGP_ERR_HIP. */
 gsgp_status gsgp_eval_population(gsgp_handle* h, const int32_t* h_codes, const double* h_consts);
 
 /* Algorithm 1's loop body, n_gens times: variation draws (tournaments),
@@ -182,7 +197,10 @@ gsgp_status gsgp_generation_replay(gsgp_handle* h, int32_t n_gens, const gsgp_re
                                    const gsgp_gen_stats* h_elite, gsgp_gen_stats* h_stats);
 
 /* Device scratch bytes gsgp_reconstruct needs for (run, gen, individual) on
- * n new cases.  Reads the ancestry record (synchronises the stream).
+ * n new cases (the lineage's generation-0 and pool programs on n cases, two
+ * generations of its ancestors, the replay lists, and spill stacks when a
+ * program's stack exceeds an LDS column).  Reads the ancestry record
+ * (synchronises the stream).
  * Errors: GSGP_ERR_ARG, GSGP_ERR_STATE. */
 gsgp_status gsgp_reconstruct_scratch_size(gsgp_handle* h, int32_t run, int32_t gen,
                                           int32_t individual, int64_t n, size_t* bytes);
@@ -203,27 +221,41 @@ gsgp_status gsgp_reconstruct(gsgp_handle* h, int32_t run, int32_t gen, int32_t i
 /* Compact model of a mutation-only lineage (the paper's own loop; GSM,
  * Section 2, and the lineage structures of Section 2.1 stage 3): individual
  * `individual` of generation `gen` of run `run` equals
- * T(x) + sum_j w_j * sigmoid(R_j(x)), with T the generation-0 population tree
- * *h_tree (HOST) and R_j the pool trees (genomes from gsgp_get_genomes).
- * h_weights (HOST, r doubles) receives w, accumulated forward generation by
- * generation (w[r1] += ms, then w[r2] -= ms).  Reads the ancestry record
- * (synchronises the stream).
+ * c + b * T(x) + sum_j w_j * sigmoid(R_j(x)), with T the generation-0
+ * population tree *h_tree (HOST) and R_j the pool trees (genomes from
+ * gsgp_get_genomes).  h_affine (HOST, 2 doubles) receives (c, b), which are
+ * (0, 1) without local search; h_weights (HOST, r doubles) receives w.  Both
+ * are accumulated forward generation by generation: with the step's
+ * offspring scaling (alpha, beta) ((0, 1) without local search),
+ * c = alpha + beta c, b = beta b, w = beta w, then w[r1] += beta ms and
+ * w[r2] -= beta ms.  Reads the ancestry record (synchronises the stream).
  * Errors: GSGP_ERR_ARG, GSGP_ERR_STATE, GSGP_ERR_UNSUPPORTED (the lineage
  * contains a crossover), GSGP_ERR_HIP. */
 gsgp_status gsgp_export_linear(gsgp_handle* h, int32_t run, int32_t gen, int32_t individual,
-                               int32_t* h_tree, double* h_weights);
+                               int32_t* h_tree, double* h_affine, double* h_weights);
 
 /* ---- inspection (HOST outputs; each synchronises the stream) ---------- */
+/* These return the state Algorithm 1 keeps between its steps: the
+ * population's fitness and semantics (the S_P matrix and the fitness vector
+ * of Algorithm 1's loop, Section 2.2), the squashed pool (the random
+ * functions R_u of GSM, Section 2), the variation draws and survival
+ * decisions that form the lineage structures (Section 2.1 stage 3), the
+ * per-generation summaries the paper writes to its two output files
+ * (Section 3.3) and the generation-0 genomes (CreatePopulation, Section 2.2
+ * "Initialization"). */
 
-/* Current generation number (0 after gsgp_eval_population). */
+/* Current generation number (0 after gsgp_eval_population); Algorithm 1's
+ * generation counter. */
 gsgp_status gsgp_current_generation(gsgp_handle* h, int32_t* gen);
 
-/* Train and test RMSE of the current population of `run` (m FP64 each). */
+/* Train and test RMSE of the current population of `run` (m FP64 each):
+ * ComputeFitness's output (Section 2.2 "Fitness computation"). */
 gsgp_status gsgp_get_fitness(gsgp_handle* h, int32_t run, double* h_train, double* h_test);
 
 /* Semantics of `run` as FP64: which = 0 the current population
  * [m][n_train + n_test], which = 1 the squashed pool sigma(S_R)
- * [r][n_train + n_test]; train cases then test cases in each row. */
+ * [r][n_train + n_test]; train cases then test cases in each row
+ * (ComputeSemantics / GSM outputs, Algorithm 1). */
 gsgp_status gsgp_get_semantics(gsgp_handle* h, int32_t run, int32_t which, double* h_out);
 
 /* Rows row0 .. row0 + n_rows - 1 of the same (h_out: [n_rows][n_train +
@@ -232,18 +264,41 @@ gsgp_status gsgp_get_semantics(gsgp_handle* h, int32_t run, int32_t which, doubl
 gsgp_status gsgp_get_semantics_rows(gsgp_handle* h, int32_t run, int32_t which, int32_t row0, int32_t n_rows,
                                     double* h_out);
 
+/* Cases case0 .. case0 + n_cases - 1 (train cases first, then test cases, as
+ * in a row of gsgp_get_semantics) of every row (h_out: [m or r][n_cases]
+ * FP64), copying only those cases from the device: for inspecting a slice of
+ * the fitness cases of a large run.
+ * Errors: GSGP_ERR_ARG (range outside [0, n_train + n_test)), GSGP_ERR_STATE,
+ * GSGP_ERR_HIP. */
+gsgp_status gsgp_get_semantics_cases(gsgp_handle* h, int32_t run, int32_t which, int64_t case0, int64_t n_cases,
+                                     double* h_out);
+
 /* Variation records of generations gen0 .. gen0 + n_gens - 1 (1-based,
- * <= current), [n_gens][m].  raw = 1 returns the draws as made; raw = 0
- * returns the lineage view, where the offspring replaced by an elite copy
- * shows op 2 with p1 = the elite parent. */
+ * <= current), [n_gens][m]: the draws of the paper's auxiliary kernels
+ * before GSM (Section 2.2) that, with the survival decisions, make up the
+ * lineage structures (Section 2.1 stage 3).  raw = 1 returns the draws as
+ * made; raw = 0 returns the lineage view, where the offspring replaced by an
+ * elite copy shows op 2 with p1 = the elite parent. */
 gsgp_status gsgp_get_records(gsgp_handle* h, int32_t run, int32_t gen0, int32_t n_gens,
                              int32_t raw, gsgp_record* h_out);
 
-/* Summaries of generations gen0 .. gen0 + n_gens - 1 (0 = initial). */
+/* Summaries of generations gen0 .. gen0 + n_gens - 1 (0 = initial): best
+ * train RMSE and the same individual's test RMSE, the two values per
+ * generation the paper writes to its output files (Section 3.3), plus the
+ * survival decision. */
 gsgp_status gsgp_get_stats(gsgp_handle* h, int32_t run, int32_t gen0, int32_t n_gens,
                            gsgp_gen_stats* h_out);
 
-/* Generation-0 genomes of `run`: [m + r][k] codes and constants. */
+/* Local search scaling (GSGP_FLAG_LOCAL_SEARCH) of every individual of
+ * generations gen0 .. gen0 + n_gens - 1 (0 = initial, <= current):
+ * h_out [n_gens][m][2] (alpha, beta); the individual's semantics are
+ * alpha + beta * (its operator's output), an elite copy carries its source's
+ * scaling, and generation 0 is (0, 1).  Without local search every entry is
+ * (0, 1). */
+gsgp_status gsgp_get_scaling(gsgp_handle* h, int32_t run, int32_t gen0, int32_t n_gens, double* h_out);
+
+/* Generation-0 genomes of `run`: [m + r][k] codes and constants
+ * (CreatePopulation's output, Section 2.2 "Initialization"). */
 gsgp_status gsgp_get_genomes(gsgp_handle* h, int32_t run, int32_t* h_codes, double* h_consts);
 
 /* ---- measurement ------------------------------------------------------ */

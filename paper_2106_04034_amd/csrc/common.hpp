@@ -25,10 +25,16 @@ constexpr int kWave = 64;
 // Interpreter work unit: a block of kInterpCases cases (kWave lanes x 2 cases).
 constexpr int kInterpCases = 128;
 constexpr int kMaxTournament = 64;
-// Deepest stack (values, top included) a compiled genome may need: the
-// interpreter keeps the top two values in registers and depth - 2 per lane
-// in LDS, at most 64 KiB for one wave.
-constexpr int kMaxStack = 65;
+// The interpreter keeps the top two stack values in registers and the rest
+// (depth - 2 values per lane) in a lane-strided column: in LDS up to this
+// many values (63 x 2 cases x 64 lanes x 8 B = 63 KiB, one wave per block),
+// beyond it in a global-memory region of the workspace that a spill pass of
+// kSpillWaves waves shares, one column per wave.
+constexpr int kMaxLdsSlots = 63;
+constexpr int kSpillWaves = 128;
+// Stack values below the top two that a genome of k genes can need: its
+// deepest stack up to its last valid function is at most k - 1 values.
+constexpr int64_t max_need(int64_t k) { return k > 3 ? k - 3 : 0; }
 // Programs whose LDS stack needs at most this many values per lane run in
 // the first interpreter pass with a small LDS column per wave (8 waves per
 // SIMD); the few deeper ones run in a second pass sized for the deepest.
@@ -70,7 +76,8 @@ struct RunDev {
   void* sigR;               // squashed pool semantics, [r][ld]
   void* y;                  // target, [ld], storage type, zero pads
   double* X;                // features, feature-major [l][ld], zero pads
-  double* part;             // chunk partial sums of squared residuals, [nch][m]
+  double* part;             // chunk partial sums of squared residuals, [nch][m]; with local
+                            // search the generation's sums of o, o^2 and o * t, [nch][3][m]
   double* F[2];             // train RMSE ping-pong, [m]
   double* Ft[2];            // test RMSE ping-pong, [m]
   gsgp_record* rec;         // variation draws, [gmax][m]; generation g at g - 1
@@ -84,6 +91,8 @@ struct RunDev {
   int32_t* need;            // LDS stack values per lane each program needs, [m + r]
   int32_t* deep;            // programs with need > kShallowSlots, [m + r] (kStDeepCount used)
   int32_t* state;           // [kStWords]
+  double* ls;               // local search: (alpha, beta) of every individual, [gmax + 1][m][2]
+  double* tsum;             // local search: sum t and sum t^2 over train, then over test cases
   int64_t n_train, n_test;  // real cases
   int64_t tr_pad, te_pad;   // padded segment lengths
   int64_t ld;               // row stride (tr_pad + te_pad)
@@ -102,6 +111,7 @@ struct Params {
   int32_t m, r, k, gmax;
   int32_t tsize, ms_random;
   int32_t n_runs, precision;
+  int32_t ls, pad1;                // ls: least-squares scaling of every variation offspring
   uint64_t t_xo, t_func, t_feat;  // event thresholds floor(p * 2^32)
   double ms, erc_lo, erc_hi;
   uint32_t seed;
@@ -170,9 +180,15 @@ hipError_t launch_compile(const RunDev* d_runs, const Params& p, hipStream_t s);
 // second pass over each run's deep list, at most deep_max programs per run.
 hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_blocks, int slots,
                             int32_t deep_max, hipStream_t s);
+// Third pass: every program on a deep list whose need exceeds kMaxLdsSlots,
+// with its stack in `spill` (kSpillWaves columns of slots x 2 x 64 doubles).
+hipError_t launch_interpret_spill(const RunDev* d_runs, const Params& p, double* spill, int slots,
+                                  hipStream_t s);
 hipError_t launch_vary(const RunDev* d_runs, const Params& p, const VaryLaunch& lc, bool rows_only,
                        hipStream_t s);
 hipError_t launch_fitness(const RunDev* d_runs, const Params& p, bool init, hipStream_t s);
+// Local search: sums of the stored target over each run's train and test cases.
+hipError_t launch_target_sums(const RunDev* d_runs, const Params& p, hipStream_t s);
 hipError_t launch_survive(const RunDev* d_runs, const Params& p, int32_t total_blocks, int mode,
                           hipStream_t s);
 // Reconstruction helpers.
@@ -181,13 +197,14 @@ hipError_t launch_transpose(const double* X, int64_t n, int32_t l, double* Xfm, 
 hipError_t launch_interpret_list(const int32_t* ops, const double* opv, const int32_t* nops,
                                  int32_t k, const int32_t* prog, const int32_t* squash,
                                  int32_t nprog, const double* Xfm, int64_t ld, int64_t n,
-                                 double* out, int slots, hipStream_t s);
+                                 double* out, int slots, double* spill, hipStream_t s);
 struct ReplayNode {
   int32_t op;     // 0 mutation, 1 crossover, 2 copy
   int32_t a, b;   // source slots (previous generation); b = -1 unless crossover
   int32_t r1, r2; // pool slots
   int32_t out;    // destination slot
   double ms;
+  double alpha, beta;  // local search: the offspring is alpha + beta * (operator output)
 };
 hipError_t launch_replay_nodes(const ReplayNode* nodes, int32_t nnodes, const double* prev,
                                const double* pool, double* next, int64_t ld, int64_t n,

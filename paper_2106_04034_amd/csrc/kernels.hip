@@ -231,9 +231,9 @@ __global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs
   int32_t prev = 0;  // the last op word written, ops[n - 1]
   for (int q = 0; q < p.k; ++q) {
     const int32_t c = code[q];
-    // a depth beyond kMaxStack before the last function makes the runtime
-    // reject the genomes before any interpretation, and ops after the last
-    // function never run; the cap only keeps the field inside its bits
+    // depths before the last function are at most k - 1 <= kOpDepthMax, and
+    // ops after the last function never run; the cap only keeps the field
+    // inside its bits
     const int dfield = (depth < kOpDepthMax ? depth : kOpDepthMax) << 4;
     if (c >= 0) {
       prev = (kClsPush << 2) | kPushFeature | dfield | (c << 16);
@@ -290,14 +290,16 @@ __global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs
 // output of its last function (the Out register), 0.0 if none runs.
 // X is feature-major in global memory, row stride ld; one case block's
 // features stay in L2 while the block's programs run.
-template <int V, bool BAKED>
+typedef GSGP_LDS double* LdsStack;        // stack column in LDS
+typedef GSGP_GLOBAL double* GlobalStack;  // stack column in the workspace (spill pass)
+
+template <int V, bool BAKED, typename Stack>
 __device__ __forceinline__ void eval_program(const int32_t* ops, const double* opv, int n, const double* X,
                                              int64_t ld, const int64_t (&col)[V], const bool (&ok)[V],
-                                             double* stk_lds, int lane, double (&out)[V]) {
+                                             Stack stk, int lane, double (&out)[V]) {
   constexpr int kBatch = kOpPad;
   const GSGP_CONST int32_t* cops = (const GSGP_CONST int32_t*)ops;
   const GSGP_CONST double* copv = (const GSGP_CONST double*)opv;
-  GSGP_LDS double* stk = (GSGP_LDS double*)stk_lds;
   double tos[V], nos[V];
 #pragma unroll
   for (int v = 0; v < V; ++v) {
@@ -421,6 +423,28 @@ static_assert(kInterpTile == kInterpCases, "the runtime plans kInterpCases-case 
 // count as a launch argument instead of a constant cost 3 %.
 constexpr int kInterpProgsPerWave = 1;
 
+// Writes one program's values for one case block: population rows as they
+// are, pool rows squashed by the logistic function (the random functions R_u
+// of GSM, Section 2); padding columns as exact zeros.
+template <typename T>
+__device__ __forceinline__ void store_program(const RunDev& R, const Params& p, int prog,
+                                              const int64_t (&col)[kInterpV], const bool (&ok)[kInterpV],
+                                              const double (&out)[kInterpV]) {
+  const bool pool = prog >= p.m;
+  T* dst = pool ? (T*)R.sigR : (T*)R.S[0];
+  const int64_t nrows = pool ? p.r : p.m;
+  const int64_t row = pool ? prog - p.m : prog;
+#pragma unroll
+  for (int v = 0; v < kInterpV; ++v) {
+    if (!ok[v]) continue;
+    const int64_t c = col[v];
+    const bool real = c < R.n_train || (c >= R.tr_pad && c < R.tr_pad + R.n_test);
+    double val = out[v];
+    if (pool) val = 1.0 / (1.0 + exp(-val));
+    dst[tiled_index(R.tr_pad, R.te_pad, R.nch_tr, chunk_cases(sizeof(T)), nrows, row, c)] = real ? (T)val : (T)0;
+  }
+}
+
 // ComputeSemantics(P) and ComputeSemantics(R) (Algorithm 1).  A block takes
 // one block of 128 cases of one run and a group of programs; each wave
 // interprets kInterpProgsPerWave programs on the block's cases.  The LDS
@@ -463,24 +487,49 @@ __global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ ru
     } else {
       if (idx >= rows) break;
       prog = idx;
-      if (uni(cload(&R.need[prog])) > slots) continue;  // left to the deep pass
     }
+    // programs deeper than this pass's column are left to a later pass
+    if (uni(cload(&R.need[prog])) > slots) continue;
     double out[kInterpV];
     eval_program<kInterpV, true>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k, uni(cload(&R.nops[prog])),
-                           R.X, ld, col, ok, stk, lane, out);
-    const bool pool = prog >= p.m;
-    T* dst = pool ? (T*)R.sigR : (T*)R.S[0];
-    const int64_t nrows = pool ? p.r : p.m;
-    const int64_t row = pool ? prog - p.m : prog;
+                                 R.X, ld, col, ok, (LdsStack)stk, lane, out);
+    store_program<T>(R, p, prog, col, ok, out);
+  }
+}
+
+// Third pass: the deep-list programs whose stack exceeds the largest LDS
+// column (need > kMaxLdsSlots).  kSpillWaves waves, one per block, each own
+// a column of `slots` x kInterpV x 64 doubles in `spill` (lane-strided as in
+// LDS, so every stack access is one coalesced 512-byte row) and sweep the
+// (program, case block) tasks of every run in turn.
+template <typename T>
+__global__ __launch_bounds__(64) void k_interpret_spill(const RunDev* __restrict__ runs, Params p, double* spill,
+                                                        int slots) {
+  const int lane = threadIdx.x & 63;
+  const int w = blockIdx.x;
+  double* stk = spill + (int64_t)w * slots * kInterpV * kWave;
+  for (int run = 0; run < p.n_runs; ++run) {
+    const RunDev& R = runs[run];
+    const int cnt = uni(cload(&R.state[kStDeepCount]));
+    const int64_t cblocks = (R.ld + kInterpTile - 1) / kInterpTile;
+    const int64_t tasks = (int64_t)cnt * cblocks;
+    for (int64_t t = w; t < tasks; t += gridDim.x) {
+      const int j = (int)(t / cblocks);
+      const int64_t cb = t - (int64_t)j * cblocks;
+      const int prog = uni(cload(&R.deep[j]));
+      const int need = uni(cload(&R.need[prog]));
+      if (need <= kMaxLdsSlots || need > slots) continue;  // LDS passes took it; never beyond the column
+      int64_t col[kInterpV];
+      bool ok[kInterpV];
 #pragma unroll
-    for (int v = 0; v < kInterpV; ++v) {
-      if (!ok[v]) continue;
-      const int64_t c = col[v];
-      const bool real = c < R.n_train || (c >= R.tr_pad && c < R.tr_pad + R.n_test);
-      double val = out[v];
-      if (pool) val = 1.0 / (1.0 + exp(-val));
-      dst[tiled_index(R.tr_pad, R.te_pad, R.nch_tr, chunk_cases(sizeof(T)), nrows, row, c)] =
-          real ? (T)val : (T)0;
+      for (int v = 0; v < kInterpV; ++v) {
+        col[v] = cb * kInterpTile + v * kWave + lane;
+        ok[v] = col[v] < R.ld;
+      }
+      double out[kInterpV];
+      eval_program<kInterpV, true>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k,
+                                   uni(cload(&R.nops[prog])), R.X, R.ld, col, ok, (GlobalStack)stk, lane, out);
+      store_program<T>(R, p, prog, col, ok, out);
     }
   }
 }
@@ -655,6 +704,103 @@ __device__ __forceinline__ void vary_offspring(const gsgp_record* rc, const T* S
   if (lane == 0) *part_out = sse;
 }
 
+// Local search form of vary_offspring.  Stored rows are the operators'
+// outputs; individual p's semantics are alpha_p + beta_p * S[p] with its
+// scaling from the generation's table `lsg` ([m][2]), applied here as the
+// parents are read (so scaling costs no extra pass over the rows).  The
+// offspring row is stored unscaled, and the chunk's sums of o, o^2 and o * t
+// (FP64, lane then butterfly, over the real cases only) go to part_out[0],
+// part_out[m], part_out[2 m]; the fitness kernel fits the offspring's own
+// scaling from them.  Real cases of the chunk are its first `real` columns.
+template <typename T, bool FULL, int NJ>
+__device__ __forceinline__ void vary_offspring_ls(const gsgp_record* rc, const double* lsg, const T* Sc, const T* gc,
+                                                  T* dst, int lane, int64_t len, int64_t real,
+                                                  const typename VecOf<T>::type (&t)[NJ], double* part_out,
+                                                  int64_t m) {
+  typedef typename VecOf<T>::type VT;
+  constexpr int N = VecOf<T>::N;
+  constexpr int64_t kChunk = chunk_cases(sizeof(T));
+  const int64_t stride = FULL ? kChunk : len;
+  const int op = uni(cload(&rc->op));
+  const int p1 = uni(cload(&rc->p1));
+  const int r1 = uni(cload(&rc->r1));
+  const int second = uni(op == 1 ? cload(&rc->p2) : cload(&rc->r2));
+  const T ms = (T)cload(&rc->ms);
+  const T* A = Sc + (int64_t)p1 * stride;
+  const T* B = (op == 1 ? Sc : gc) + (int64_t)(op == 1 ? second : r1) * stride;
+  const T* C = gc + (int64_t)(op == 1 ? r1 : second) * stride;
+  // scaling of the parents (the second one only for crossover); in the FP32
+  // forms the coefficients are rounded to FP32 and kept finite
+  auto coef = [](double v) {
+    if constexpr (std::is_same<T, float>::value) return (T)fmin(fmax(v, -kFltMax), kFltMax);
+    else return (T)v;
+  };
+  const T a1 = coef(cload(&lsg[2 * (int64_t)p1])), b1 = coef(cload(&lsg[2 * (int64_t)p1 + 1]));
+  const T a2 = op == 1 ? coef(cload(&lsg[2 * (int64_t)second])) : (T)0;
+  const T b2 = op == 1 ? coef(cload(&lsg[2 * (int64_t)second + 1])) : (T)1;
+  const bool padded = real < len;
+  bool ok[NJ];
+  VT x[NJ], y[NJ], z[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int e = j * kWave * N + lane * N;
+    ok[j] = FULL || e < len;
+    if (ok[j]) {
+      x[j] = gload<VT>(A + e);
+      y[j] = gload<VT>(B + e);
+      z[j] = gload<VT>(C + e);
+    } else {
+      x[j] = VT(0);
+      y[j] = VT(0);
+      z[j] = VT(0);
+    }
+  }
+  auto clamp = [](VT v) {
+    if constexpr (std::is_same<T, float>::value) {
+#pragma unroll
+      for (int c = 0; c < N; ++c) v[c] = __builtin_amdgcn_fmed3f(v[c], (T)-kFltMax, (T)kFltMax);
+    }
+    return v;
+  };
+  double so = 0.0, soo = 0.0, sot = 0.0;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int e = j * kWave * N + lane * N;
+    const VT xe = clamp(a1 + b1 * x[j]);
+    VT o;
+    if (op == 1) {
+      // GSC on the parents' semantics: O = T1 * sR[r1] + T2 * (1 - sR[r1])
+      const VT ye = clamp(a2 + b2 * y[j]);
+      o = clamp(xe * z[j] + ye * ((T)1 - z[j]));
+    } else {
+      // GSM: O = T + ms * (sR[r1] - sR[r2])
+      o = clamp(xe + ms * (y[j] - z[j]));
+    }
+    if (padded) {
+#pragma unroll
+      for (int c = 0; c < N; ++c) o[c] = (e + c < real) ? o[c] : (T)0;  // pads stay exact zeros
+    }
+    if (ok[j]) {
+      gstore_nt<VT>(o, dst + e);
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        const double ov = (double)o[c];
+        so += ov;
+        soo += ov * ov;
+        sot += ov * (double)t[j][c];
+      }
+    }
+  }
+  so = wave_sum(so);
+  soo = wave_sum(soo);
+  sot = wave_sum(sot);
+  if (lane == 0) {
+    part_out[0] = so;
+    part_out[m] = soo;
+    part_out[2 * m] = sot;
+  }
+}
+
 // Partial sums of an existing row (generation-0 fitness).
 template <typename T, int PREC, bool FULL, int NJ>
 __device__ __forceinline__ void row_partial(const T* row, int lane, int64_t len,
@@ -674,7 +820,7 @@ __device__ __forceinline__ void row_partial(const T* row, int lane, int64_t len,
   if (lane == 0) *part_out = sse;
 }
 
-template <typename T, int PREC, bool ROWS, bool FULL>
+template <typename T, int PREC, bool ROWS, bool FULL, bool LS>
 __device__ __forceinline__ void vary_task(const RunDev& R, const Params& p, const VaryLaunch& lc, int chunk,
                                           int grp, int lane, int wave) {
   typedef typename VecOf<T>::type VT;
@@ -705,6 +851,18 @@ __device__ __forceinline__ void vary_task(const RunDev& R, const Params& p, cons
   if constexpr (ROWS) {
     for (int i = grp * lc.opb + wave; i < i_end; i += lc.waves)
       row_partial<T, PREC, FULL, NJ>(Sc + (int64_t)i * stride, lane, len, t, yv, part + i);
+  } else if constexpr (LS) {
+    const gsgp_record* recs = R.rec + (int64_t)gen * p.m;
+    const double* lsg = R.ls + (int64_t)gen * p.m * 2;
+    // real cases of this chunk: the segment's real cases past its first column
+    const bool train = chunk < R.nch_tr;
+    const int64_t first = train ? cs : cs - R.tr_pad;
+    int64_t real = (train ? R.n_train : R.n_test) - first;
+    real = real < 0 ? 0 : (real > len ? len : real);
+    double* part3 = R.part + (int64_t)chunk * 3 * p.m;
+    for (int i = grp * lc.opb + wave; i < i_end; i += lc.waves)
+      vary_offspring_ls<T, FULL, NJ>(recs + i, lsg, Sc, gc, Oc + (int64_t)i * stride, lane, len, real, t,
+                                     part3 + i, p.m);
   } else {
     const gsgp_record* recs = R.rec + (int64_t)gen * p.m;
     for (int i = grp * lc.opb + wave; i < i_end; i += lc.waves)
@@ -723,7 +881,7 @@ __device__ __forceinline__ void vary_task(const RunDev& R, const Params& p, cons
 // 16-byte stores and writes the chunk's sum of squared residuals.  With
 // ROWS the kernel only forms the partial sums of the current population
 // (generation-0 fitness).
-template <typename T, int PREC, bool ROWS, bool LOOP>
+template <typename T, int PREC, bool ROWS, bool LOOP, bool LS>
 __global__ __launch_bounds__(512) void k_vary(const RunDev* __restrict__ runs, Params p, VaryLaunch lc) {
   constexpr int kChunk = chunk_cases(sizeof(T));
   const int lane = threadIdx.x & 63;
@@ -754,11 +912,14 @@ __global__ __launch_bounds__(512) void k_vary(const RunDev* __restrict__ runs, P
     const int grp = (int)(local - (int64_t)chunk * lc.ogroups);
     const ChunkGeom g = chunk_geom(R.tr_pad, R.te_pad, R.nch_tr, chunk, kChunk);
     if (g.len == kChunk)
-      vary_task<T, PREC, ROWS, true>(R, p, lc, chunk, grp, lane, wave);
+      vary_task<T, PREC, ROWS, true, LS>(R, p, lc, chunk, grp, lane, wave);
     else
-      vary_task<T, PREC, ROWS, false>(R, p, lc, chunk, grp, lane, wave);
+      vary_task<T, PREC, ROWS, false, LS>(R, p, lc, chunk, grp, lane, wave);
   }
 }
+
+// (the generation-0 partial sums never scale: every individual starts with
+// alpha = 0, beta = 1)
 
 // ComputeFitness (Section 2.2 "Fitness computation"): a block takes 64
 // individuals of one run (lane = individual, so the chunk-major partial sums
@@ -810,6 +971,113 @@ __global__ __launch_bounds__(kFitWaves * 64) void k_fitness(const RunDev* __rest
     const int dst = init ? 0 : ((R.state[kStGen] + 1) & 1);
     R.F[dst][i] = sqrt(s / (double)R.n_train);
     R.Ft[dst][i] = R.n_test > 0 ? sqrt(st / (double)R.n_test) : 0.0;
+  }
+}
+
+// Local search fitness: each offspring's least-squares scaling and the RMSE
+// of its scaled semantics, in closed form from its chunk sums (o, o^2, o * t
+// over the real cases; laid out [chunk][3][m]) and the run's target sums.
+// With n cases, D = So2 - So^2 / n (n times the variance of o) and
+// Sxy = Sot - So * St / n:
+//   beta = Sxy / D,  alpha = (St - beta * So) / n,
+//   SSE_train = (Stt - St^2 / n) - beta * Sxy   (residual orthogonal to 1, o),
+//   SSE_test = sum (alpha + beta o - t)^2 expanded over the test sums.
+// A numerically constant offspring (D <= 1e-10 * So2) keeps alpha = 0,
+// beta = 1 and SSE = So2 - 2 Sot + Stt.  Chunk sums combine as in k_fitness.
+// The scaling goes to the table row of the offspring generation.
+__global__ __launch_bounds__(kFitWaves * 64) void k_fitness_ls(const RunDev* __restrict__ runs, Params p,
+                                                                int32_t blocks_per_run) {
+  __shared__ double sh[6][kFitWaves][kWave];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int run = blockIdx.x / blocks_per_run;
+  const int i = (blockIdx.x - run * blocks_per_run) * kWave + lane;
+  const RunDev& R = runs[run];
+  const bool live = i < p.m;
+  const int ii = live ? i : 0;
+  const int64_t m = p.m;
+  const int nt = R.nch_tr, ne = R.nch - R.nch_tr;
+  const int a0 = (int)((int64_t)nt * wave / kFitWaves), a1 = (int)((int64_t)nt * (wave + 1) / kFitWaves);
+  const int b0 = nt + (int)((int64_t)ne * wave / kFitWaves), b1 = nt + (int)((int64_t)ne * (wave + 1) / kFitWaves);
+  for (int q = 0; q < 3; ++q) {
+    double s = 0.0, st = 0.0;
+    for (int c = a0; c < a1; ++c) s += R.part[((int64_t)c * 3 + q) * m + ii];
+    for (int c = b0; c < b1; ++c) st += R.part[((int64_t)c * 3 + q) * m + ii];
+    sh[q][wave][lane] = s;
+    sh[3 + q][wave][lane] = st;
+  }
+  __syncthreads();
+  if (wave == 0 && live) {
+    double v[6];
+    for (int q = 0; q < 6; ++q) {
+      v[q] = sh[q][0][lane];
+      for (int w = 1; w < kFitWaves; ++w) v[q] += sh[q][w][lane];
+    }
+    const double n = (double)R.n_train, So = v[0], Soo = v[1], Sot = v[2];
+    const double St = R.tsum[0], Stt = R.tsum[1];
+    const double D = Soo - So * So / n;
+    double alpha = 0.0, beta = 1.0, sse;
+    if (D > 1e-10 * Soo) {
+      const double Sxy = Sot - So * St / n;
+      beta = Sxy / D;
+      alpha = (St - beta * So) / n;
+      sse = (Stt - St * St / n) - beta * Sxy;
+    } else {
+      sse = Soo - 2.0 * Sot + Stt;
+    }
+    sse = sse > 0.0 ? sse : 0.0;
+    double sse_te = 0.0;
+    if (R.n_test > 0) {
+      const double ne_ = (double)R.n_test, Se = v[3], See = v[4], Set = v[5];
+      const double Ste = R.tsum[2], Stte = R.tsum[3];
+      // sum (alpha + beta o - t)^2 = beta^2 See + sum (alpha - t)^2 + 2 beta sum o (alpha - t)
+      sse_te = beta * beta * See + (ne_ * alpha * alpha - 2.0 * alpha * Ste + Stte) +
+               2.0 * beta * (alpha * Se - Set);
+      sse_te = sse_te > 0.0 ? sse_te : 0.0;
+    }
+    const int g1 = R.state[kStGen] + 1;
+    const int dst = g1 & 1;
+    R.F[dst][i] = sqrt(sse / n);
+    R.Ft[dst][i] = R.n_test > 0 ? sqrt(sse_te / (double)R.n_test) : 0.0;
+    R.ls[((int64_t)g1 * m + i) * 2] = alpha;
+    R.ls[((int64_t)g1 * m + i) * 2 + 1] = beta;
+  }
+}
+
+// Local search: sums of the stored target over a run's real train and test
+// cases (one block per run; thread-strided FP64 sums, then a fixed-order LDS
+// tree, so the bits never vary).  Also writes generation 0's scaling table
+// row (alpha = 0, beta = 1).
+template <typename T>
+__global__ __launch_bounds__(256) void k_target_sums(const RunDev* __restrict__ runs, Params p) {
+  __shared__ double sh[4][256];
+  const RunDev& R = runs[blockIdx.x];
+  const T* y = (const T*)R.y;
+  double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
+  for (int64_t k = threadIdx.x; k < R.n_train; k += blockDim.x) {
+    const double v = (double)y[k];
+    a += v;
+    b += v * v;
+  }
+  for (int64_t k = threadIdx.x; k < R.n_test; k += blockDim.x) {
+    const double v = (double)y[R.tr_pad + k];
+    c += v;
+    d += v * v;
+  }
+  sh[0][threadIdx.x] = a;
+  sh[1][threadIdx.x] = b;
+  sh[2][threadIdx.x] = c;
+  sh[3][threadIdx.x] = d;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) R.tsum[threadIdx.x] = sh[threadIdx.x][0];
+  for (int i = threadIdx.x; i < p.m; i += blockDim.x) {
+    R.ls[2 * (int64_t)i] = 0.0;
+    R.ls[2 * (int64_t)i + 1] = 1.0;
   }
 }
 
@@ -1089,6 +1357,11 @@ __global__ __launch_bounds__(256) void k_survive(const RunDev* __restrict__ runs
       if (copied) {
         FO[dst] = FP[src];
         FtO[dst] = FtP[src];
+        if (p.ls) {  // the copy keeps its source's scaling
+          const int64_t m64 = m;
+          R.ls[((int64_t)(gen + 1) * m64 + dst) * 2] = R.ls[((int64_t)gen * m64 + src) * 2];
+          R.ls[((int64_t)(gen + 1) * m64 + dst) * 2 + 1] = R.ls[((int64_t)gen * m64 + src) * 2 + 1];
+        }
       }
       R.state[kStGen] = gen + 1;
     }
@@ -1104,6 +1377,37 @@ __global__ __launch_bounds__(256) void k_transpose(const double* __restrict__ X,
   for (int f = 0; f < l; ++f) Xfm[(int64_t)f * ld + c] = c < n ? X[c * l + f] : 0.0;
 }
 
+// One (program, 128-case block) task of the list interpreter: nprog
+// programs (prog[j], squashed by the logistic when squash[j]) on cases of
+// the feature-major Xfm, out[j][ld].
+template <typename Stack>
+__device__ __forceinline__ void list_task(const int32_t* ops, const double* opv, const int32_t* nops, int32_t k,
+                                          const int32_t* prog, const int32_t* squash, int32_t nprog,
+                                          const double* Xfm, int64_t ld, int64_t n, double* out, int64_t task,
+                                          Stack stk, int lane) {
+  const int64_t cb = task / nprog;
+  const int j = (int)(task - cb * nprog);
+  const int pr = uni(prog[j]);
+  int64_t col[kInterpV];
+  bool ok[kInterpV];
+#pragma unroll
+  for (int v = 0; v < kInterpV; ++v) {
+    col[v] = cb * (kWave * kInterpV) + v * kWave + lane;
+    ok[v] = col[v] < ld;
+  }
+  double val[kInterpV];
+  eval_program<kInterpV, false>(ops + (int64_t)pr * k, opv + (int64_t)pr * k, uni(nops[pr]), Xfm, ld, col, ok, stk,
+                                lane, val);
+  const bool sq = squash[j] != 0;
+#pragma unroll
+  for (int v = 0; v < kInterpV; ++v) {
+    if (!ok[v]) continue;
+    double x = val[v];
+    if (sq) x = 1.0 / (1.0 + exp(-x));
+    out[(int64_t)j * ld + col[v]] = col[v] < n ? x : 0.0;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_interpret_list(const int32_t* __restrict__ ops,
                                                         const double* __restrict__ opv,
                                                         const int32_t* __restrict__ nops, int32_t k,
@@ -1117,28 +1421,25 @@ __global__ __launch_bounds__(256) void k_interpret_list(const int32_t* __restric
   const int wave = uni(threadIdx.x >> 6);
   const int64_t task = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
   if (task >= total) return;
-  const int64_t cb = task / nprog;
-  const int j = (int)(task - cb * nprog);
-  const int pr = uni(prog[j]);
-  int64_t col[kInterpV];
-  bool ok[kInterpV];
-#pragma unroll
-  for (int v = 0; v < kInterpV; ++v) {
-    col[v] = cb * (kWave * kInterpV) + v * kWave + lane;
-    ok[v] = col[v] < ld;
-  }
-  double val[kInterpV];
   double* stk = lds + wave * slots * kInterpV * kWave;
-  eval_program<kInterpV, false>(ops + (int64_t)pr * k, opv + (int64_t)pr * k, uni(nops[pr]), Xfm, ld, col, ok, stk, lane,
-                         val);
-  const bool sq = squash[j] != 0;
-#pragma unroll
-  for (int v = 0; v < kInterpV; ++v) {
-    if (!ok[v]) continue;
-    double x = val[v];
-    if (sq) x = 1.0 / (1.0 + exp(-x));
-    out[(int64_t)j * ld + col[v]] = col[v] < n ? x : 0.0;
-  }
+  list_task(ops, opv, nops, k, prog, squash, nprog, Xfm, ld, n, out, task, (LdsStack)stk, lane);
+}
+
+// The same with stacks deeper than an LDS column: kSpillWaves one-wave
+// blocks, each with a column of `slots` x kInterpV x 64 doubles in `spill`,
+// sweep the tasks.
+__global__ __launch_bounds__(64) void k_interpret_list_spill(const int32_t* __restrict__ ops,
+                                                             const double* __restrict__ opv,
+                                                             const int32_t* __restrict__ nops, int32_t k,
+                                                             const int32_t* __restrict__ prog,
+                                                             const int32_t* __restrict__ squash,
+                                                             int32_t nprog, const double* __restrict__ Xfm,
+                                                             int64_t ld, int64_t n, double* __restrict__ out,
+                                                             double* spill, int slots, int64_t total) {
+  const int lane = threadIdx.x & 63;
+  double* stk = spill + (int64_t)blockIdx.x * slots * kInterpV * kWave;
+  for (int64_t task = blockIdx.x; task < total; task += gridDim.x)
+    list_task(ops, opv, nops, k, prog, squash, nprog, Xfm, ld, n, out, task, (GlobalStack)stk, lane);
 }
 
 __global__ __launch_bounds__(256) void k_replay_nodes(const ReplayNode* __restrict__ nodes,
@@ -1158,6 +1459,9 @@ __global__ __launch_bounds__(256) void k_replay_nodes(const ReplayNode* __restri
   } else {
     o = a;
   }
+  // local search: the offspring's recorded scaling (never for copies, and
+  // skipped when it is the identity so that unscaled runs keep their bits)
+  if (nd.op != 2 && (nd.alpha != 0.0 || nd.beta != 1.0)) o = nd.alpha + nd.beta * o;
   next[(int64_t)nd.out * ld + c] = o;
 }
 
@@ -1215,6 +1519,7 @@ hipError_t launch_compile(const RunDev* d_runs, const Params& p, hipStream_t s) 
 hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_blocks, int slots,
                             int32_t deep_max, hipStream_t s) {
   if (slots < 1) slots = 1;
+  if (slots > kMaxLdsSlots) return hipErrorInvalidValue;  // deeper stacks take the spill pass
   if (deep_max == 0) return hipSuccess;
   // one LDS stack column block per wave, at most 64 KiB per block
   const int waves = interp_waves(slots);
@@ -1232,19 +1537,40 @@ hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_
   return hipGetLastError();
 }
 
+hipError_t launch_interpret_spill(const RunDev* d_runs, const Params& p, double* spill, int slots,
+                                  hipStream_t s) {
+  if (slots <= kMaxLdsSlots) return hipSuccess;
+  if (!spill) return hipErrorInvalidValue;
+  if (p.precision == GSGP_FP64)
+    hipLaunchKernelGGL((k_interpret_spill<double>), dim3(kSpillWaves), dim3(kWave), 0, s, d_runs, p, spill, slots);
+  else
+    hipLaunchKernelGGL((k_interpret_spill<float>), dim3(kSpillWaves), dim3(kWave), 0, s, d_runs, p, spill, slots);
+  return hipGetLastError();
+}
+
 template <typename T, int PREC>
 void launch_vary_as(const RunDev* d_runs, const Params& p, const VaryLaunch& lc, bool rows_only, bool one_shot,
                     dim3 grid, dim3 block, hipStream_t s) {
   if (rows_only) {
     if (one_shot)
-      hipLaunchKernelGGL((k_vary<T, PREC, true, false>), grid, block, 0, s, d_runs, p, lc);
+      hipLaunchKernelGGL((k_vary<T, PREC, true, false, false>), grid, block, 0, s, d_runs, p, lc);
     else
-      hipLaunchKernelGGL((k_vary<T, PREC, true, true>), grid, block, 0, s, d_runs, p, lc);
+      hipLaunchKernelGGL((k_vary<T, PREC, true, true, false>), grid, block, 0, s, d_runs, p, lc);
+  } else if (p.ls) {
+    // local search sums are FP64 in every form, so one instance per storage type
+    if constexpr (PREC != GSGP_FP32_KAHAN) {
+      if (one_shot)
+        hipLaunchKernelGGL((k_vary<T, PREC, false, false, true>), grid, block, 0, s, d_runs, p, lc);
+      else
+        hipLaunchKernelGGL((k_vary<T, PREC, false, true, true>), grid, block, 0, s, d_runs, p, lc);
+    } else {
+      launch_vary_as<T, GSGP_FP32>(d_runs, p, lc, rows_only, one_shot, grid, block, s);
+    }
   } else {
     if (one_shot)
-      hipLaunchKernelGGL((k_vary<T, PREC, false, false>), grid, block, 0, s, d_runs, p, lc);
+      hipLaunchKernelGGL((k_vary<T, PREC, false, false, false>), grid, block, 0, s, d_runs, p, lc);
     else
-      hipLaunchKernelGGL((k_vary<T, PREC, false, true>), grid, block, 0, s, d_runs, p, lc);
+      hipLaunchKernelGGL((k_vary<T, PREC, false, true, false>), grid, block, 0, s, d_runs, p, lc);
   }
 }
 
@@ -1273,8 +1599,20 @@ hipError_t launch_vary(const RunDev* d_runs, const Params& p, const VaryLaunch& 
 
 hipError_t launch_fitness(const RunDev* d_runs, const Params& p, bool init, hipStream_t s) {
   const int32_t per_run = (p.m + kWave - 1) / kWave;
-  hipLaunchKernelGGL(k_fitness, dim3((unsigned)(per_run * p.n_runs)), dim3(kFitWaves * kWave), 0, s, d_runs, p,
-                     per_run, init ? 1 : 0);
+  if (p.ls && !init)
+    hipLaunchKernelGGL(k_fitness_ls, dim3((unsigned)(per_run * p.n_runs)), dim3(kFitWaves * kWave), 0, s, d_runs,
+                       p, per_run);
+  else
+    hipLaunchKernelGGL(k_fitness, dim3((unsigned)(per_run * p.n_runs)), dim3(kFitWaves * kWave), 0, s, d_runs, p,
+                       per_run, init ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_target_sums(const RunDev* d_runs, const Params& p, hipStream_t s) {
+  if (p.precision == GSGP_FP64)
+    hipLaunchKernelGGL(k_target_sums<double>, dim3((unsigned)p.n_runs), dim3(256), 0, s, d_runs, p);
+  else
+    hipLaunchKernelGGL(k_target_sums<float>, dim3((unsigned)p.n_runs), dim3(256), 0, s, d_runs, p);
   return hipGetLastError();
 }
 
@@ -1306,11 +1644,17 @@ hipError_t launch_transpose(const double* X, int64_t n, int32_t l, double* Xfm, 
 hipError_t launch_interpret_list(const int32_t* ops, const double* opv, const int32_t* nops,
                                  int32_t k, const int32_t* prog, const int32_t* squash,
                                  int32_t nprog, const double* Xfm, int64_t ld, int64_t n,
-                                 double* out, int slots, hipStream_t s) {
+                                 double* out, int slots, double* spill, hipStream_t s) {
   if (nprog <= 0) return hipSuccess;
   if (slots < 1) slots = 1;
   const int64_t cblocks = (ld + kWave * kInterpV - 1) / (kWave * kInterpV);
   const int64_t total = cblocks * nprog;
+  if (slots > kMaxLdsSlots) {
+    if (!spill) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_interpret_list_spill, dim3(kSpillWaves), dim3(kWave), 0, s, ops, opv, nops, k, prog,
+                       squash, nprog, Xfm, ld, n, out, spill, slots, total);
+    return hipGetLastError();
+  }
   const int waves = interp_waves(slots);
   const size_t shmem = (size_t)waves * slots * kInterpV * kWave * sizeof(double);
   hipLaunchKernelGGL(k_interpret_list, dim3(blocks_for(total, waves)), dim3(waves * kWave),

@@ -52,6 +52,7 @@ struct RunPlan {
   int64_t n_train, n_test, tr_pad, te_pad, ld;
   int32_t l, nch_tr, nch_te;
   size_t X, y, S0, S1, sigR, part, F0, F1, Ft0, Ft1, rec, stats, elite_in, code, cval, ops, opv, nops, need, deep;
+  size_t ls, tsum;
   size_t end;
 };
 
@@ -67,10 +68,13 @@ struct Guard {
 };
 
 struct Plan {
-  size_t runs_dev, src_ptrs, state, total;
+  size_t runs_dev, src_ptrs, state, spill, spill_bytes, total;
   std::vector<RunPlan> runs;
   std::vector<Guard> guards;
 };
+
+// Flags that change what a run computes (the others change only how).
+constexpr uint32_t kResultFlags = GSGP_FLAG_LOCAL_SEARCH;
 
 gsgp_status validate_config(const gsgp_config* c) {
   if (!c) return fail(GSGP_ERR_ARG, "config is NULL");
@@ -93,7 +97,8 @@ gsgp_status validate_config(const gsgp_config* c) {
       std::fabs(c->erc_lo) > 3.0e38 || std::fabs(c->erc_hi) > 3.0e38)
     return fail(GSGP_ERR_ARG, "constant range must be finite with erc_lo <= erc_hi");
   if (c->precision < GSGP_FP64 || c->precision > GSGP_FP32_KAHAN) return fail(GSGP_ERR_ARG, "unknown precision %d", c->precision);
-  if ((c->flags & ~(GSGP_FLAG_NO_GRAPH | GSGP_FLAG_GUARDS)) != 0) return fail(GSGP_ERR_ARG, "unknown flags 0x%x", c->flags);
+  if ((c->flags & ~(GSGP_FLAG_NO_GRAPH | GSGP_FLAG_GUARDS | GSGP_FLAG_LOCAL_SEARCH)) != 0)
+    return fail(GSGP_ERR_ARG, "unknown flags 0x%x", c->flags);
   if (c->reserved != 0) return fail(GSGP_ERR_ARG, "reserved config field must be 0");
   return GSGP_OK;
 }
@@ -105,6 +110,7 @@ gsgp_status make_plan(const gsgp_config* c, const gsgp_run* runs, int32_t n_runs
   const int64_t m = c->pop_size, r = c->pool_size, k = c->genome_len, G = c->n_generations_max;
   const size_t s = storage_bytes(c->precision);
   const bool guarded = (c->flags & GSGP_FLAG_GUARDS) != 0;
+  const bool ls = (c->flags & GSGP_FLAG_LOCAL_SEARCH) != 0;
   plan->guards.clear();
   size_t off = 0;
   // reserves `bytes` at the next aligned offset, plus a guard when asked
@@ -120,6 +126,11 @@ gsgp_status make_plan(const gsgp_config* c, const gsgp_run* runs, int32_t n_runs
   plan->runs_dev = take_at(sizeof(RunDev) * n_runs, -1, "run descriptors");
   plan->src_ptrs = take_at(sizeof(double*) * 4 * n_runs, -1, "input pointers");
   plan->state = take_at(sizeof(int32_t) * kStWords * n_runs, -1, "state words");
+  // stack columns of the interpreter's spill pass, sized for the deepest
+  // stack a genome of k genes can need; none when every stack fits in LDS
+  const int64_t need_cap = max_need(k);
+  plan->spill_bytes = need_cap > kMaxLdsSlots ? sizeof(double) * kSpillWaves * need_cap * 2 * kWave : 0;
+  plan->spill = take_at(plan->spill_bytes, -1, "interpreter spill stacks");
   plan->runs.resize(n_runs);
   for (int32_t i = 0; i < n_runs; ++i) {
     const gsgp_run& d = runs[i];
@@ -146,7 +157,8 @@ gsgp_status make_plan(const gsgp_config* c, const gsgp_run* runs, int32_t n_runs
     p.S0 = take_at(s * m * p.ld, i, "S[0]");
     p.S1 = take_at(s * m * p.ld, i, "S[1]");
     p.sigR = take_at(s * r * p.ld, i, "sigmoid(S_R)");
-    p.part = take_at(sizeof(double) * (p.nch_tr + p.nch_te) * m, i, "chunk partial sums");
+    // chunk partial sums: one per individual, three with local search
+    p.part = take_at(sizeof(double) * (p.nch_tr + p.nch_te) * m * (ls ? 3 : 1), i, "chunk partial sums");
     p.F0 = take_at(8 * m, i, "F[0]");
     p.F1 = take_at(8 * m, i, "F[1]");
     p.Ft0 = take_at(8 * m, i, "Ft[0]");
@@ -161,6 +173,9 @@ gsgp_status make_plan(const gsgp_config* c, const gsgp_run* runs, int32_t n_runs
     p.nops = take_at(4 * (m + r), i, "program lengths");
     p.need = take_at(4 * (m + r), i, "program stack needs");
     p.deep = take_at(4 * (m + r), i, "deep program list");
+    // local search: the scaling table of every generation and the target sums
+    p.ls = take_at(ls ? sizeof(double) * 2 * (G + 1) * m : 0, i, "scaling table");
+    p.tsum = take_at(ls ? sizeof(double) * 4 : 0, i, "target sums");
     p.end = off;
   }
   plan->total = off;
@@ -358,6 +373,24 @@ gsgp_status check_run(gsgp_handle* h, int32_t run) {
   return GSGP_OK;
 }
 
+// Local search: rows row0 .. row0 + n_rows - 1 of the current population
+// are stored unscaled; their semantics are alpha + beta * S with the current
+// generation's scaling (FP64, the same operations the variation kernel
+// applies when it reads a parent).  out holds n_rows rows of `cols` values.
+gsgp_status apply_scaling(gsgp_handle* h, int32_t run, int32_t row0, int32_t n_rows, int64_t cols, double* out) {
+  if (!(h->cfg.flags & GSGP_FLAG_LOCAL_SEARCH)) return GSGP_OK;
+  std::vector<double> ab((size_t)2 * n_rows);
+  const double* table = h->runs_h[run].ls + ((int64_t)h->gen * h->cfg.pop_size + row0) * 2;
+  HIPCHK(h, hipMemcpy(ab.data(), table, sizeof(double) * ab.size(), hipMemcpyDeviceToHost));
+  for (int32_t i = 0; i < n_rows; ++i) {
+    const double a = ab[2 * i], b = ab[2 * i + 1];
+    if (a == 0.0 && b == 1.0) continue;
+    double* row = out + (int64_t)i * cols;
+    for (int64_t c = 0; c < cols; ++c) row[c] = a + b * row[c];
+  }
+  return GSGP_OK;
+}
+
 // Unpacks a chunk-tiled semantic buffer (see chunk_geom) into FP64 rows of
 // n_train + n_test cases.
 template <typename T>
@@ -450,6 +483,8 @@ gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_ru
   p.erc_hi = cfg->erc_hi;
   p.seed = cfg->seed;
   p.pad = 0;
+  p.ls = (cfg->flags & GSGP_FLAG_LOCAL_SEARCH) ? 1 : 0;
+  p.pad1 = 0;
 
   char* ws = h->ws;
   h->runs_d = (RunDev*)(ws + plan.runs_dev);
@@ -481,6 +516,8 @@ gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_ru
     R.nops = (int32_t*)(ws + q.nops);
     R.need = (int32_t*)(ws + q.need);
     R.deep = (int32_t*)(ws + q.deep);
+    R.ls = (double*)(ws + q.ls);
+    R.tsum = (double*)(ws + q.tsum);
     R.state = state + (size_t)kStWords * i;
     R.n_train = q.n_train;
     R.n_test = q.n_test;
@@ -601,16 +638,22 @@ gsgp_status eval_impl(gsgp_handle* h, const int32_t* h_codes, const double* h_co
     deepest = std::max(deepest, h->pinned[kStWords * r + kStMaxDepth]);
     deep_max = std::max(deep_max, h->pinned[kStWords * r + kStDeepCount]);
   }
-  if (deepest > kMaxStack) {
-    h->evaluated = false;
-    return fail(GSGP_ERR_UNSUPPORTED, "a genome needs a stack of %d values; at most %d are supported", deepest, kMaxStack);
-  }
   h->slots = std::max(1, deepest - 2);  // the top two values live in registers
-  // every program that fits a small LDS column, then the deep ones
+  // the deepest stack up to a genome's last valid function is at most k - 1
+  // values, which sized the spill stacks; anything else is a broken invariant
+  if ((int64_t)h->slots > std::max<int64_t>(1, max_need(p.k))) {
+    h->poisoned = true;
+    return fail(GSGP_ERR_STATE, "compiled stack depth %d exceeds the bound for genomes of %d genes", deepest, p.k);
+  }
+  // every program that fits a small LDS column, then the deeper ones in an
+  // LDS column sized for them, then those beyond any LDS column
   HIPCHK(h, launch_interpret(h->runs_d, p, h->interp_tasks, std::min(h->slots, kShallowSlots), -1, h->stream));
   if (h->slots > kShallowSlots)
-    HIPCHK(h, launch_interpret(h->runs_d, p, h->interp_tasks, h->slots, deep_max, h->stream));
+    HIPCHK(h, launch_interpret(h->runs_d, p, h->interp_tasks, std::min(h->slots, kMaxLdsSlots), deep_max, h->stream));
+  if (h->slots > kMaxLdsSlots)
+    HIPCHK(h, launch_interpret_spill(h->runs_d, p, (double*)(h->ws + h->plan.spill), h->slots, h->stream));
   if (ev) HIPCHK(h, hipEventRecord(ev[2], h->stream));
+  if (p.ls) HIPCHK(h, launch_target_sums(h->runs_d, p, h->stream));  // and generation 0's scaling
   HIPCHK(h, launch_vary(h->runs_d, p, h->rows, true, h->stream));
   HIPCHK(h, launch_fitness(h->runs_d, p, true, h->stream));
   HIPCHK(h, launch_survive(h->runs_d, p, h->surv_blocks, kSurvInit, h->stream));
@@ -762,6 +805,66 @@ gsgp_status gsgp_get_semantics_rows(gsgp_handle* h, int32_t run, int32_t which, 
     to_f64<double>(raw, n_rows, R, h_out);
   else
     to_f64<float>(raw, n_rows, R, h_out);
+  if (which == 0) return apply_scaling(h, run, row0, n_rows, R.n_train + R.n_test, h_out);
+  return GSGP_OK;
+}
+
+gsgp_status gsgp_get_semantics_cases(gsgp_handle* h, int32_t run, int32_t which, int64_t case0, int64_t n_cases,
+                                     double* h_out) {
+  gsgp_status st = check_run(h, run);
+  if (st != GSGP_OK) return st;
+  if (which != 0 && which != 1) return fail(GSGP_ERR_ARG, "which must be 0 (population) or 1 (pool)");
+  if (!h_out) return fail(GSGP_ERR_ARG, "h_out is NULL");
+  const RunDev& R = h->runs_h[run];
+  const int64_t n_all = R.n_train + R.n_test;
+  if (case0 < 0 || n_cases < 1 || case0 + n_cases > n_all)
+    return fail(GSGP_ERR_ARG, "cases %lld..%lld not in [0, %lld)", (long long)case0, (long long)(case0 + n_cases - 1),
+                (long long)n_all);
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  const int64_t rows = which == 0 ? h->cfg.pop_size : h->cfg.pool_size;
+  const size_t s = storage_bytes(h->cfg.precision);
+  const int64_t CH = chunk_cases((int)s);
+  const char* from = (const char*)(which == 0 ? R.S[h->gen & 1] : R.sigR);
+  // the requested cases as padded-column ranges: train part, then test part
+  struct Piece {
+    int64_t col0, col1, out0;
+  };
+  Piece pieces[2];
+  int np = 0;
+  const int64_t c1 = case0 + n_cases;
+  if (case0 < R.n_train) pieces[np++] = Piece{case0, std::min(c1, R.n_train), 0};
+  if (c1 > R.n_train) {
+    const int64_t t0 = std::max(case0, R.n_train) - R.n_train, t1 = c1 - R.n_train;
+    pieces[np++] = Piece{R.tr_pad + t0, R.tr_pad + t1, std::max(case0, R.n_train) - case0};
+  }
+  std::vector<char> buf;
+  for (int q = 0; q < np; ++q) {
+    const Piece& pc = pieces[q];
+    const int32_t first = pc.col0 < R.tr_pad ? (int32_t)(pc.col0 / CH) : R.nch_tr + (int32_t)((pc.col0 - R.tr_pad) / CH);
+    for (int32_t c = first; c < R.nch; ++c) {
+      const ChunkGeom g = chunk_geom(R.tr_pad, R.te_pad, R.nch_tr, c, CH);
+      const int64_t lo = std::max(pc.col0, g.cs), hi = std::min(pc.col1, g.cs + g.len);
+      if (g.cs >= pc.col1) break;
+      if (lo >= hi) continue;
+      // rows x (hi - lo) sub-block of the chunk block: row i at rows * cs + i * len + (lo - cs)
+      const int64_t w = hi - lo;
+      buf.resize((size_t)rows * w * s);
+      HIPCHK(h, hipMemcpy2D(buf.data(), (size_t)w * s, from + (size_t)(rows * g.cs + (lo - g.cs)) * s, (size_t)g.len * s,
+                            (size_t)w * s, (size_t)rows, hipMemcpyDeviceToHost));
+      const int64_t o = pc.out0 + (lo - pc.col0);
+      for (int64_t i = 0; i < rows; ++i) {
+        double* dst = h_out + i * n_cases + o;
+        if (s == 8) {
+          const double* src = (const double*)buf.data() + i * w;
+          for (int64_t k = 0; k < w; ++k) dst[k] = src[k];
+        } else {
+          const float* src = (const float*)buf.data() + i * w;
+          for (int64_t k = 0; k < w; ++k) dst[k] = (double)src[k];
+        }
+      }
+    }
+  }
+  if (which == 0) return apply_scaling(h, run, 0, (int32_t)rows, n_cases, h_out);
   return GSGP_OK;
 }
 
@@ -799,6 +902,25 @@ gsgp_status gsgp_get_stats(gsgp_handle* h, int32_t run, int32_t gen0, int32_t n_
     return fail(GSGP_ERR_ARG, "summaries of generations %d..%d are not available (current %d)", gen0, gen0 + n_gens - 1, h->gen);
   HIPCHK(h, hipStreamSynchronize(h->stream));
   HIPCHK(h, hipMemcpy(h_out, h->runs_h[run].stats + gen0, sizeof(gsgp_gen_stats) * n_gens, hipMemcpyDeviceToHost));
+  return GSGP_OK;
+}
+
+gsgp_status gsgp_get_scaling(gsgp_handle* h, int32_t run, int32_t gen0, int32_t n_gens, double* h_out) {
+  gsgp_status st = check_run(h, run);
+  if (st != GSGP_OK) return st;
+  if (!h_out || n_gens < 1 || gen0 < 0 || (int64_t)gen0 + n_gens - 1 > h->gen)
+    return fail(GSGP_ERR_ARG, "scaling of generations %d..%d is not available (current %d)", gen0, gen0 + n_gens - 1, h->gen);
+  const int64_t m = h->cfg.pop_size;
+  if (!(h->cfg.flags & GSGP_FLAG_LOCAL_SEARCH)) {
+    for (int64_t q = 0; q < (int64_t)n_gens * m; ++q) {
+      h_out[2 * q] = 0.0;
+      h_out[2 * q + 1] = 1.0;
+    }
+    return GSGP_OK;
+  }
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  HIPCHK(h, hipMemcpy(h_out, h->runs_h[run].ls + (int64_t)gen0 * m * 2, sizeof(double) * 2 * m * n_gens,
+                      hipMemcpyDeviceToHost));
   return GSGP_OK;
 }
 
@@ -955,9 +1077,10 @@ struct Lineage {
   std::vector<int32_t> pool;               // pool trees used, sorted
   std::vector<gsgp_record> rec;            // [gen][m]
   std::vector<gsgp_gen_stats> stats;       // [gen + 1]
+  std::vector<double> ls;                  // local search: [gen + 1][m][2] scaling, else empty
   size_t max_slots = 1, total_nodes = 0;
   int64_t ld = 0;
-  size_t off_X = 0, off_pool = 0, off_A = 0, off_B = 0, off_prog = 0, off_nodes = 0, total = 0;
+  size_t off_X = 0, off_pool = 0, off_A = 0, off_B = 0, off_prog = 0, off_nodes = 0, off_spill = 0, total = 0;
 };
 
 gsgp_status walk_lineage(gsgp_handle* h, int32_t run, int32_t gen, int32_t individual, int64_t n, Lineage* L) {
@@ -969,6 +1092,10 @@ gsgp_status walk_lineage(gsgp_handle* h, int32_t run, int32_t gen, int32_t indiv
   if (gen > 0) {
     HIPCHK(h, hipMemcpy(L->rec.data(), R.rec, sizeof(gsgp_record) * gen * m, hipMemcpyDeviceToHost));
     HIPCHK(h, hipMemcpy(L->stats.data(), R.stats, sizeof(gsgp_gen_stats) * (gen + 1), hipMemcpyDeviceToHost));
+    if (h->cfg.flags & GSGP_FLAG_LOCAL_SEARCH) {
+      L->ls.resize((size_t)(gen + 1) * m * 2);
+      HIPCHK(h, hipMemcpy(L->ls.data(), R.ls, sizeof(double) * L->ls.size(), hipMemcpyDeviceToHost));
+    }
   }
   std::vector<std::set<int32_t>> need(gen + 1);
   std::set<int32_t> pool;
@@ -1011,6 +1138,8 @@ gsgp_status walk_lineage(gsgp_handle* h, int32_t run, int32_t gen, int32_t indiv
   L->off_B = take(sizeof(double) * L->max_slots * L->ld);
   L->off_prog = take(sizeof(int32_t) * 2 * (L->need[0].size() + L->pool.size() + 2));
   L->off_nodes = take(sizeof(ReplayNode) * std::max<size_t>(1, L->total_nodes));
+  // stack columns for programs deeper than an LDS column (spill interpreter)
+  L->off_spill = take(h->slots > kMaxLdsSlots ? sizeof(double) * kSpillWaves * h->slots * 2 * kWave : 0);
   L->total = off;
   return GSGP_OK;
 }
@@ -1033,23 +1162,34 @@ gsgp_status gsgp_reconstruct_scratch_size(gsgp_handle* h, int32_t run, int32_t g
 }
 
 gsgp_status gsgp_export_linear(gsgp_handle* h, int32_t run, int32_t gen, int32_t individual, int32_t* h_tree,
-                               double* h_weights) {
+                               double* h_affine, double* h_weights) {
   gsgp_status st = check_run(h, run);
   if (st != GSGP_OK) return st;
   if (gen < 0 || gen > h->gen) return fail(GSGP_ERR_ARG, "generation %d not in [0, %d]", gen, h->gen);
   if (individual < 0 || individual >= h->cfg.pop_size) return fail(GSGP_ERR_ARG, "individual out of range");
-  if (!h_tree || !h_weights) return fail(GSGP_ERR_ARG, "NULL output pointer");
+  if (!h_tree || !h_affine || !h_weights) return fail(GSGP_ERR_ARG, "NULL output pointer");
   const int32_t m = h->cfg.pop_size, r = h->cfg.pool_size;
+  const bool scaled = (h->cfg.flags & GSGP_FLAG_LOCAL_SEARCH) != 0;
   const RunDev& R = h->runs_h[run];
   HIPCHK(h, hipStreamSynchronize(h->stream));
   std::vector<gsgp_record> rec((size_t)gen * m);
   std::vector<gsgp_gen_stats> stats((size_t)gen + 1);
+  std::vector<double> ls;
   if (gen > 0) {
     HIPCHK(h, hipMemcpy(rec.data(), R.rec, sizeof(gsgp_record) * gen * m, hipMemcpyDeviceToHost));
     HIPCHK(h, hipMemcpy(stats.data(), R.stats, sizeof(gsgp_gen_stats) * (gen + 1), hipMemcpyDeviceToHost));
+    if (scaled) {
+      ls.resize((size_t)(gen + 1) * m * 2);
+      HIPCHK(h, hipMemcpy(ls.data(), R.ls, sizeof(double) * ls.size(), hipMemcpyDeviceToHost));
+    }
   }
-  // walk back to the generation-0 tree, keeping the mutations in order
-  std::vector<const gsgp_record*> muts;
+  // walk back to the generation-0 tree, keeping the mutations in order with
+  // the generation and index of the offspring each one made
+  struct Step {
+    const gsgp_record* d;
+    int32_t g, i;
+  };
+  std::vector<Step> steps;
   int32_t i = individual;
   for (int32_t g = gen; g >= 1; --g) {
     const gsgp_gen_stats& s = stats[g];
@@ -1059,16 +1199,29 @@ gsgp_status gsgp_export_linear(gsgp_handle* h, int32_t run, int32_t gen, int32_t
     }
     const gsgp_record& d = rec[(size_t)(g - 1) * m + i];
     if (d.op == 1) return fail(GSGP_ERR_UNSUPPORTED, "the lineage contains a crossover at generation %d", g);
-    muts.push_back(&d);
+    steps.push_back(Step{&d, g, i});
     i = d.p1;
   }
-  // forward accumulation: w[r1] += ms, then w[r2] -= ms, generation by generation
+  // forward, generation by generation: with the step's scaling (alpha, beta)
+  // (0 and 1 without local search), c = alpha + beta c, b = beta b,
+  // w = beta w, then w[r1] += beta ms and w[r2] -= beta ms
   std::vector<double> w(r, 0.0);
-  for (auto it = muts.rbegin(); it != muts.rend(); ++it) {
-    w[(*it)->r1] += (*it)->ms;
-    w[(*it)->r2] -= (*it)->ms;
+  double c = 0.0, b = 1.0;
+  for (auto it = steps.rbegin(); it != steps.rend(); ++it) {
+    double alpha = 0.0, beta = 1.0;
+    if (scaled) {
+      alpha = ls[((size_t)it->g * m + it->i) * 2];
+      beta = ls[((size_t)it->g * m + it->i) * 2 + 1];
+    }
+    c = alpha + beta * c;
+    b = beta * b;
+    for (double& x : w) x = beta * x;
+    w[it->d->r1] += beta * it->d->ms;
+    w[it->d->r2] -= beta * it->d->ms;
   }
   *h_tree = i;
+  h_affine[0] = c;
+  h_affine[1] = b;
   std::copy(w.begin(), w.end(), h_weights);
   return GSGP_OK;
 }
@@ -1095,6 +1248,7 @@ gsgp_status gsgp_reconstruct(gsgp_handle* h, int32_t run, int32_t gen, int32_t i
   double* bufB = (double*)(sc + L.off_B);
   int32_t* prog = (int32_t*)(sc + L.off_prog);
   ReplayNode* nodes = (ReplayNode*)(sc + L.off_nodes);
+  double* spill = h->slots > kMaxLdsSlots ? (double*)(sc + L.off_spill) : nullptr;
 
   // host-side lists: generation-0 programs, pool programs, replay nodes
   const size_t n0 = L.need[0].size(), np = L.pool.size();
@@ -1126,6 +1280,8 @@ gsgp_status gsgp_reconstruct(gsgp_handle* h, int32_t run, int32_t gen, int32_t i
       nd.r1 = -1;
       nd.r2 = -1;
       nd.ms = 0.0;
+      nd.alpha = 0.0;
+      nd.beta = 1.0;
       if (s.elite_copied && i == s.elite_dst) {
         nd.op = 2;
         nd.a = prev_slot.at(s.elite_src);
@@ -1139,6 +1295,10 @@ gsgp_status gsgp_reconstruct(gsgp_handle* h, int32_t run, int32_t gen, int32_t i
         } else {
           nd.r2 = pool_slot.at(d.r2);
           nd.ms = d.ms;
+        }
+        if (!L.ls.empty()) {
+          nd.alpha = L.ls[((size_t)g * m + i) * 2];
+          nd.beta = L.ls[((size_t)g * m + i) * 2 + 1];
         }
       }
       all_nodes.push_back(nd);
@@ -1155,9 +1315,9 @@ gsgp_status gsgp_reconstruct(gsgp_handle* h, int32_t run, int32_t gen, int32_t i
   const int32_t* d_sqp = d_progp + np + 1;
   HIPCHK(h, launch_transpose(d_X, n, R.l, Xfm, L.ld, h->stream));
   HIPCHK(h, launch_interpret_list(R.ops, R.opv, R.nops, h->cfg.genome_len, d_prog0, d_sq0, (int32_t)n0, Xfm, L.ld, n,
-                                  bufA, h->slots, h->stream));
+                                  bufA, h->slots, spill, h->stream));
   HIPCHK(h, launch_interpret_list(R.ops, R.opv, R.nops, h->cfg.genome_len, d_progp, d_sqp, (int32_t)np, Xfm, L.ld, n,
-                                  pool, h->slots, h->stream));
+                                  pool, h->slots, spill, h->stream));
   double* cur = bufA;
   double* nxt = bufB;
   for (int32_t g = 1; g <= gen; ++g) {
@@ -1208,11 +1368,18 @@ namespace {
 
 constexpr uint64_t kCkptMagic = 0x5450434B50475347ull;  // "GSGPCKPT"
 
+// Everything that decides a run's draws and values is in the header and
+// must match the loading handle: sizes, precision, seed and every operator
+// setting (tournament, crossover probability, step and its randomness, gene
+// probabilities, constant range, the flags that change results).
 struct CkptHeader {
   uint64_t magic;
-  int32_t version, n_runs, m, r, k, G, precision, gen, slots, pad;
-  uint32_t seed, flags;
+  int32_t version, n_runs, m, r, k, G, precision, gen, slots, tsize, ms_random, pad;
+  uint32_t seed, result_flags;
+  double p_crossover, mutation_step, p_function, p_feature, erc_lo, erc_hi;
 };
+constexpr int32_t kCkptVersion = 4;  // 4: every operator setting in the header
+static_assert(sizeof(CkptHeader) == 112, "no padding between header fields");
 
 struct CkptPiece {
   size_t off;    // workspace offset
@@ -1240,14 +1407,19 @@ std::vector<CkptPiece> ckpt_pieces(const gsgp_handle* h) {
     out.push_back({q.ops, 4 * (size_t)((m + r) * k)});
     out.push_back({q.opv, 8 * (size_t)((m + r) * k)});
     out.push_back({q.nops, 4 * (size_t)(m + r)});
+    if (h->cfg.flags & GSGP_FLAG_LOCAL_SEARCH) {
+      out.push_back({q.ls, sizeof(double) * 2 * (size_t)(m * (h->gen + 1))});
+      out.push_back({q.tsum, sizeof(double) * 4});
+    }
   }
   return out;
 }
 
 CkptHeader ckpt_header(const gsgp_handle* h) {
-  CkptHeader c{};
+  CkptHeader c;
+  std::memset(&c, 0, sizeof c);  // padding included: headers compare bytewise
   c.magic = kCkptMagic;
-  c.version = 3;  // 3: fused push-function ops, feature row offsets in opv
+  c.version = kCkptVersion;
   c.n_runs = h->n_runs;
   c.m = h->cfg.pop_size;
   c.r = h->cfg.pool_size;
@@ -1256,9 +1428,25 @@ CkptHeader ckpt_header(const gsgp_handle* h) {
   c.precision = h->cfg.precision;
   c.gen = h->gen;
   c.slots = h->slots;
+  c.tsize = h->cfg.tournament_size;
+  c.ms_random = h->cfg.ms_random;
   c.seed = h->cfg.seed;
-  c.flags = h->cfg.flags;
+  c.result_flags = h->cfg.flags & kResultFlags;
+  c.p_crossover = h->cfg.p_crossover;
+  c.mutation_step = h->cfg.mutation_step;
+  c.p_function = h->cfg.p_function;
+  c.p_feature = h->cfg.p_feature;
+  c.erc_lo = h->cfg.erc_lo;
+  c.erc_hi = h->cfg.erc_hi;
   return c;
+}
+
+// The run-defining part of two headers is equal (the generation and the
+// compiled stack depth are the saved state, not configuration).
+bool same_configuration(CkptHeader a, CkptHeader b) {
+  a.gen = b.gen;
+  a.slots = b.slots;
+  return std::memcmp(&a, &b, sizeof a) == 0;
 }
 
 size_t ckpt_bytes(const gsgp_handle* h, const std::vector<CkptPiece>& pieces) {
@@ -1311,11 +1499,12 @@ gsgp_status gsgp_checkpoint_load(gsgp_handle* h, const void* h_buf, size_t bytes
   if (!h_buf || bytes < sizeof(CkptHeader)) return fail(GSGP_ERR_ARG, "no checkpoint");
   CkptHeader c;
   std::memcpy(&c, h_buf, sizeof c);
-  if (c.magic != kCkptMagic || c.version != 3) return fail(GSGP_ERR_ARG, "not a checkpoint of this library");
-  if (c.n_runs != h->n_runs || c.m != h->cfg.pop_size || c.r != h->cfg.pool_size || c.k != h->cfg.genome_len ||
-      c.G != h->cfg.n_generations_max || c.precision != h->cfg.precision || c.seed != h->cfg.seed)
-    return fail(GSGP_ERR_ARG, "the checkpoint was taken with another configuration");
-  if (c.gen < 0 || c.gen > h->cfg.n_generations_max || c.slots < 1 || c.slots > kMaxStack)
+  if (c.magic != kCkptMagic || c.version != kCkptVersion) return fail(GSGP_ERR_ARG, "not a checkpoint of this library");
+  if (!same_configuration(c, ckpt_header(h)))
+    return fail(GSGP_ERR_ARG, "the checkpoint was taken with another configuration (sizes, precision, seed or "
+                              "operator settings differ)");
+  if (c.gen < 0 || c.gen > h->cfg.n_generations_max || c.slots < 1 ||
+      (int64_t)c.slots > std::max<int64_t>(1, max_need(h->cfg.genome_len)))
     return fail(GSGP_ERR_ARG, "corrupt checkpoint header");
   const char* in = (const char*)h_buf + sizeof c;
   if (bytes < sizeof c + sizeof(int64_t) * 2 * h->n_runs) return fail(GSGP_ERR_ARG, "truncated checkpoint");

@@ -22,6 +22,7 @@ FP64, FP32, FP32_KAHAN = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp32_kahan": FP32_KAHAN}
 FLAG_NO_GRAPH = 1
 FLAG_GUARDS = 2
+FLAG_LOCAL_SEARCH = 4
 
 STATUS = {0: "GSGP_OK", -1: "GSGP_ERR_ARG", -2: "GSGP_ERR_STATE", -3: "GSGP_ERR_WORKSPACE",
           -4: "GSGP_ERR_NONFINITE", -5: "GSGP_ERR_HIP", -6: "GSGP_ERR_UNSUPPORTED"}
@@ -37,8 +38,9 @@ EXPORTS = [
     "gsgp_workspace_size", "gsgp_init", "gsgp_eval_population", "gsgp_generation",
     "gsgp_generation_replay", "gsgp_reconstruct_scratch_size", "gsgp_reconstruct", "gsgp_export_linear",
     "gsgp_current_generation", "gsgp_get_fitness", "gsgp_get_semantics", "gsgp_get_semantics_rows",
+    "gsgp_get_semantics_cases",
     "gsgp_get_records",
-    "gsgp_get_stats", "gsgp_get_genomes", "gsgp_time_stages", "gsgp_time_eval", "gsgp_set_launch",
+    "gsgp_get_stats", "gsgp_get_scaling", "gsgp_get_genomes", "gsgp_time_stages", "gsgp_time_eval", "gsgp_set_launch",
     "gsgp_autotune", "gsgp_checkpoint_size", "gsgp_checkpoint_save", "gsgp_checkpoint_load",
     "gsgp_guard_offsets", "gsgp_destroy", "gsgp_status_string", "gsgp_last_error",
 ]
@@ -92,13 +94,15 @@ def lib():
             "gsgp_generation_replay": [P, I32, P, P, P],
             "gsgp_reconstruct_scratch_size": [P, I32, I32, I32, I64, P],
             "gsgp_reconstruct": [P, I32, I32, I32, P, I64, P, P, ctypes.c_size_t],
-            "gsgp_export_linear": [P, I32, I32, I32, P, P],
+            "gsgp_export_linear": [P, I32, I32, I32, P, P, P],
             "gsgp_current_generation": [P, P],
             "gsgp_get_fitness": [P, I32, P, P],
             "gsgp_get_semantics": [P, I32, I32, P],
             "gsgp_get_semantics_rows": [P, I32, I32, I32, I32, P],
+            "gsgp_get_semantics_cases": [P, I32, I32, I64, I64, P],
             "gsgp_get_records": [P, I32, I32, I32, I32, P],
             "gsgp_get_stats": [P, I32, I32, I32, P],
+            "gsgp_get_scaling": [P, I32, I32, I32, P],
             "gsgp_get_genomes": [P, I32, P, P],
             "gsgp_time_stages": [P, I32, P],
             "gsgp_time_eval": [P, P],
@@ -298,6 +302,15 @@ class Runner:
               "gsgp_get_semantics_rows")
         return out
 
+    def semantics_cases(self, run: int, which: int, case0: int, n_cases: int) -> np.ndarray:
+        """Cases case0 .. case0 + n_cases - 1 (train then test numbering) of
+        every population (which 0) or pool (which 1) row, FP64."""
+        rows = self.m if which == 0 else self.r
+        out = np.zeros((rows, n_cases))
+        check(lib().gsgp_get_semantics_cases(self._h, run, which, int(case0), int(n_cases), _ptr(out)),
+              "gsgp_get_semantics_cases")
+        return out
+
     def semantics(self, run: int = 0, which: int = 0) -> np.ndarray:
         n_tr, n_te, _ = self.shapes[run]
         rows = self.m if which == 0 else self.r
@@ -315,6 +328,13 @@ class Runner:
         check(lib().gsgp_get_stats(self._h, run, gen0, n, _ptr(out)), "gsgp_get_stats")
         return out
 
+    def scaling(self, run: int, gen0: int, n: int) -> np.ndarray:
+        """(alpha, beta) of every individual of generations gen0 .. gen0 + n - 1,
+        [n][m][2] (local search; (0, 1) without it)."""
+        out = np.zeros((n, self.m, 2))
+        check(lib().gsgp_get_scaling(self._h, run, gen0, n, _ptr(out)), "gsgp_get_scaling")
+        return out
+
     def genomes(self, run: int = 0):
         rows = self.m + self.r
         k = self.settings.genome_len
@@ -324,13 +344,14 @@ class Runner:
         return codes, consts
 
     def export_linear(self, run: int, gen: int, individual: int):
-        """(tree, weights): individual = tree(x) + weights . sigmoid(pool(x))
+        """(tree, c, b, weights): individual = c + b tree(x) + weights . sigmoid(pool(x))
         for a mutation-only lineage; raises GSGPError (unsupported) otherwise."""
         tree = ctypes.c_int32(0)
+        cb = np.zeros(2)
         w = np.zeros(self.r)
-        check(lib().gsgp_export_linear(self._h, run, gen, individual, ctypes.byref(tree), _ptr(w)),
+        check(lib().gsgp_export_linear(self._h, run, gen, individual, ctypes.byref(tree), _ptr(cb), _ptr(w)),
               "gsgp_export_linear")
-        return int(tree.value), w
+        return int(tree.value), float(cb[0]), float(cb[1]), w
 
     def reconstruct(self, run: int, gen: int, individual: int, X: np.ndarray) -> np.ndarray:
         torch = self.torch

@@ -38,3 +38,16 @@ def records_equal(gpu_rec, orc_rec) -> bool:
         if not np.array_equal(gpu_rec[f], orc_rec[f]):
             return False
     return True
+
+
+def oracle_records(rec):
+    """A device record array as the oracle's record dtype (same layout)."""
+    out = np.zeros(rec.shape, dtype=orc.RECORD_DTYPE)
+    for f in ("op", "p1", "p2", "r1", "r2", "ms"):
+        out[f] = rec[f]
+    return out
+
+
+def elite_of(stats):
+    """(copied, src, dst) rows from device summaries."""
+    return np.stack([stats["elite_copied"], stats["elite_src"], stats["elite_dst"]], axis=-1).astype(np.int32)

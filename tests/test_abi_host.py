@@ -47,18 +47,37 @@ def test_workspace_size_tracks_memory_complexity():
         genomes = (1024 + 512) * 127 * (4 + 8) * 2
         lower = semantic + data + record + genomes
         assert lower <= size <= lower * 1.02 + (1 << 20)
-    one = gsgp.workspace_size(gsgp.Settings(), [(500, 200, 8)])
-    two = gsgp.workspace_size(gsgp.Settings(), [(500, 200, 8), (500, 200, 8)])
+    # per-run buffers scale with the runs; with genomes of at most 66 genes
+    # every stack fits an LDS column and no spill stacks are reserved
+    short = gsgp.Settings(genome_len=66)
+    one = gsgp.workspace_size(short, [(500, 200, 8)])
+    two = gsgp.workspace_size(short, [(500, 200, 8), (500, 200, 8)])
     assert 1.9 * one < two < 2.1 * one
 
 
+def test_spill_stacks_are_sized_for_the_deepest_possible_genome():
+    """Genomes of k genes can need k - 3 stack values below the top two; past
+    63 they run in the spill pass, whose 128 wavefront columns of (k - 3) x
+    2 cases x 64 lanes doubles the workspace reserves once for all runs."""
+    runs = [(500, 200, 8)]
+    base = gsgp.workspace_size(gsgp.Settings(genome_len=66), runs)
+    for k in (67, 127, 2047):
+        extra = gsgp.workspace_size(gsgp.Settings(genome_len=k), runs) - base
+        genomes = (128 + 128) * (k - 66) * (4 + 8) * 2
+        spill = 128 * (k - 3) * 2 * 64 * 8
+        assert spill + genomes <= extra <= spill + genomes + 4096, k
+    two = gsgp.workspace_size(gsgp.Settings(genome_len=127), runs * 2) - gsgp.workspace_size(
+        gsgp.Settings(genome_len=127), runs)
+    assert two < 128 * 124 * 1024  # shared, not per run
+
+
 def test_guard_flag_adds_one_guard_per_buffer():
-    """GSGP_FLAG_GUARDS: 3 shared buffers plus 20 per run, each followed by
+    """GSGP_FLAG_GUARDS: 4 shared buffers plus 22 per run, each followed by
     a 256-byte guard (rounded up to the 256-byte buffer alignment)."""
     for runs in ([(500, 200, 8)], [(500, 200, 8), (900, 0, 3)]):
         plain = gsgp.workspace_size(gsgp.Settings(), runs)
         guarded = gsgp.workspace_size(gsgp.Settings(flags=gsgp.FLAG_GUARDS), runs)
-        n_guards = 3 + 20 * len(runs)
+        n_guards = 4 + 22 * len(runs)
         assert plain + 256 * n_guards <= guarded <= plain + 512 * n_guards
 
 
@@ -68,8 +87,8 @@ BAD_SETTINGS = [
     dict(ms_random=2), dict(p_crossover=1.5), dict(p_crossover=-0.1),
     dict(tournament_size=0, p_crossover=0.5), dict(mutation_step=-1.0),
     dict(mutation_step=float("nan")), dict(p_function=0.9, p_feature=0.2),
-    dict(erc_lo=1.0, erc_hi=-1.0), dict(erc_hi=float("inf")), dict(precision=3), dict(flags=4),
-    dict(flags=8),
+    dict(erc_lo=1.0, erc_hi=-1.0), dict(erc_hi=float("inf")), dict(precision=3), dict(flags=8),
+    dict(flags=16),
 ]
 
 

@@ -80,14 +80,28 @@ def test_gene_steps_count_pushes_and_valid_functions_up_to_the_last_function(k):
     assert bench.gene_steps(hand) == 5
 
 
-def test_traffic_comes_from_the_counter_summary_only_for_the_same_kernel_sources(monkeypatch):
-    text = open(bench.PMC_SUMMARY).read()
-    digest = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text).group(1)
-    hbm = float(re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text).group(1))
-    monkeypatch.setattr(bench, "kernel_digest", lambda: digest)
-    assert bench.traffic_from_profile(1.0) == hbm
+def test_traffic_comes_from_the_counter_summary_only_for_the_same_kernel_sources(monkeypatch, tmp_path):
+    path = tmp_path / "k_vary_x_pmc.md"
+    path.write_text("# summary\n\nhbm_bytes_per_launch: 1234567890\nkernel_source_sha256_16: 0123456789abcdef\n")
+    monkeypatch.setattr(bench, "kernel_digest", lambda: "0123456789abcdef")
+    assert bench.traffic_from_profile(str(path)) == 1234567890.0
     monkeypatch.setattr(bench, "kernel_digest", lambda: "0" * 16)
-    assert bench.traffic_from_profile(1.0) is None
+    assert bench.traffic_from_profile(str(path)) is None
+    assert bench.traffic_from_profile(str(tmp_path / "missing.md")) is None
+    for w, p in bench.PMC_SUMMARIES.items():  # committed summaries carry both fields
+        if os.path.exists(p):
+            text = open(p).read()
+            assert re.search(r"kernel_source_sha256_16:\s*[0-9a-f]{16}", text), w
+            assert re.search(r"hbm_bytes_per_launch:\s*[0-9.eE+]+", text), w
+
+
+def test_interpreter_rate_weights_each_genome_by_its_run_cases():
+    rng = np.random.default_rng(3)
+    codes = rng.integers(-5, 4, size=(6, 40)).astype(np.int32)
+    n = np.array([10, 10, 200, 200, 7, 7])
+    rate = bench.interpreter_rate_rows(codes, n, 1.0)
+    assert rate["gene_steps"] == sum(bench.gene_steps(codes[j:j + 1]) * int(n[j]) for j in range(6))
+    assert bench.interpreter_rate(codes, 50, 1.0)["gene_steps"] == bench.gene_steps(codes) * 50
 
 
 def test_kernel_digest_covers_the_kernels_and_their_shared_header(tmp_path, monkeypatch):

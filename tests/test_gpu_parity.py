@@ -16,6 +16,7 @@ import pytest
 from oracle import oracle as orc
 from paper_2106_04034_amd import gsgp, synth
 from tests.gpu_helpers import concat_sem, dataset, oracle_config, records_equal, rel_err
+from tests.gpu_helpers import elite_of as _elite_of, oracle_records as _oracle_records
 
 pytestmark = pytest.mark.gpu
 
@@ -505,9 +506,9 @@ def test_export_linear_equals_oracle_and_reconstruction():
     Xnew = np.random.default_rng(4).uniform(-1, 1, size=(77, 4))
     sig = orc.sigmoid(orc.interpret(codes[s.pop_size:], consts[s.pop_size:], Xnew))
     for i in range(s.pop_size):
-        tree, w = R.export_linear(0, G, i)
-        otree, ow = orc.export_linear(res, cfg, G, i)
-        assert tree == otree and np.array_equal(w, ow), i
+        tree, c, b, w = R.export_linear(0, G, i)
+        otree, oc, ob, ow = orc.export_linear(res, cfg, G, i)
+        assert tree == otree and np.array_equal(w, ow) and (c, b) == (oc, ob) == (0.0, 1.0), i
         val = orc.interpret(codes[tree:tree + 1], consts[tree:tree + 1], Xnew)[0] + w @ sig
         rec = R.reconstruct(0, G, i, Xnew)
         assert np.allclose(val, rec, rtol=1e-12, atol=1e-12 * np.max(np.abs(rec))), i
@@ -581,9 +582,9 @@ def test_workspace_guards_stay_intact_and_catch_an_overwrite(precision):
     R.time_eval()
     R.generation(5)
     offs = R.guard_offsets()
-    assert offs.size == 3 + 20 * 3
+    assert offs.size == 4 + 22 * 3
     base = R._ws_ptr - R._ws.data_ptr()
-    at = int(base + offs[3 + 20 + 2])  # after S[0] of run 1
+    at = int(base + offs[4 + 22 + 2])  # after S[0] of run 1
     R._ws[at:at + 4] = 0
     R.torch.cuda.synchronize()
     with pytest.raises(gsgp.GSGPError) as e:
@@ -661,3 +662,182 @@ def test_error_paths():
     with pytest.raises(gsgp.GSGPError) as e:
         _runner(s, [d2])
     assert e.value.status == -4
+
+
+def test_rejected_genomes_leave_the_run_untouched():
+    """A genome set that fails validation (a feature index beyond the run's
+    features, a constant that is not finite) is refused before any device
+    work: the run's generation, semantics, fitness, records and summaries
+    stay as they were, and the run then continues exactly as an
+    uninterrupted one."""
+    d = dataset(700, 200, 4, seed=60)
+    s = gsgp.Settings(pop_size=32, pool_size=16, n_generations_max=8, seed=61)
+    A = _runner(s, [d])
+    A.eval_population()
+    A.generation(3)
+    before = (A.current_generation(), A.semantics(0, 0), A.semantics(0, 1), A.fitness(0), A.records(0, 1, 3),
+              A.stats(0, 0, 4))
+    k, rows = s.genome_len, s.pop_size + s.pool_size
+    bad_code = np.full((rows, k), -1, np.int32)
+    bad_code[5, 3] = 4  # feature 4 of a 4-feature run
+    consts = np.zeros((rows, k))
+    nan_const = np.full((rows, k), -5, np.int32)
+    bad_val = np.zeros((rows, k))
+    bad_val[9, 0] = np.inf
+    for codes, vals in ((bad_code, consts), (nan_const, bad_val)):
+        with pytest.raises(gsgp.GSGPError) as e:
+            A.eval_population(codes, vals)
+        assert e.value.status == -1
+    after = (A.current_generation(), A.semantics(0, 0), A.semantics(0, 1), A.fitness(0), A.records(0, 1, 3),
+             A.stats(0, 0, 4))
+    assert before[0] == after[0] == 3
+    for x, y in zip(before[1:], after[1:]):
+        if isinstance(x, tuple):
+            for a, b in zip(x, y):
+                assert np.array_equal(a, b)
+        else:
+            assert np.array_equal(x, y)
+    A.generation(5)
+    B = _runner(s, [d])
+    B.eval_population()
+    B.generation(8)
+    assert np.array_equal(A.semantics(0, 0), B.semantics(0, 0))
+    assert np.array_equal(A.stats(0, 0, 9), B.stats(0, 0, 9))
+    A.close()
+    B.close()
+
+
+def _deep_stack_genomes(rng, m, r, k, l, depths):
+    """Random genomes, with row j < len(depths) replaced by a genome whose
+    stack reaches depths[j] values before its last function."""
+    codes = np.where(rng.random((m + r, k)) < 0.5, rng.integers(-4, 0, size=(m + r, k)),
+                     rng.integers(0, l, size=(m + r, k))).astype(np.int32)
+    consts = np.zeros((m + r, k))
+    for j, D in enumerate(depths):
+        codes[j], consts[j] = _deep_genome(rng, D, k, l)
+    return codes, consts
+
+
+@pytest.mark.parametrize("precision", [gsgp.FP64, gsgp.FP32])
+def test_stacks_beyond_an_lds_column_take_the_spill_pass(precision):
+    """Genomes whose stacks need more values than the largest LDS column (63
+    below the top two) are evaluated in the spill pass with their stacks in
+    the workspace: population and pool semantics equal the oracle's bit for
+    bit (FP64; FP32 is the rounding of the same values), the run then evolves
+    in step with the oracle, and lineages through such genomes reconstruct on
+    new cases (the list interpreter's spill form)."""
+    rng = np.random.default_rng(70)
+    k, l, m, r = 300, 5, 20, 8
+    depths = [66, 100, 150, 64, 65, 140, 7]   # D terminals + D - 1 functions fit in k = 300
+    codes, consts = _deep_stack_genomes(rng, m, r, k, l, depths)
+    codes[m + 1], consts[m + 1] = _deep_genome(rng, 120, k, l)   # a deep pool tree too
+    assert _stack_depths(codes[:m]).max() == 150
+    d = dataset(900, 250, l, seed=71)
+    G = 4
+    s = gsgp.Settings(pop_size=m, pool_size=r, genome_len=k, n_generations_max=G, seed=72, precision=precision)
+    R = _runner(s, [d])
+    R.eval_population(codes, consts)
+    X = np.concatenate([d.X_train, d.X_test])
+    want = orc.interpret(codes[:m], consts[:m], X)
+    got = R.semantics(0, 0)
+    if precision == gsgp.FP64:
+        assert np.array_equal(got, want)
+    else:
+        assert np.array_equal(got, want.astype(np.float32).astype(np.float64))
+    sig = orc.sigmoid(orc.interpret(codes[m:], consts[m:], X))
+    tol = 4 * np.spacing(np.maximum(np.abs(sig), 1e-300)) if precision == gsgp.FP64 else \
+        np.spacing(np.abs(sig).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(R.semantics(0, 1) - sig) <= tol)
+    R.generation(G)
+    Xnew = np.random.default_rng(73).uniform(-1, 1, size=(300, l))
+    cfg = oracle_config(s)
+    res = orc.Result(codes, consts, None, None, None, None, None, None,
+                     _oracle_records(R.records(0, 1, G)), _elite_of(R.stats(0, 1, G)))
+    res.scale = np.zeros((G + 1, m, 2))
+    res.scale[:, :, 1] = 1.0
+    for i in (0, 2, 5, m - 1):
+        assert rel_err(R.reconstruct(0, G, i, Xnew), orc.reconstruct(res, cfg, G, i, Xnew), 1.0) <= 1e-12
+    # generation 0 of the deepest genome itself, through the spill list interpreter
+    assert rel_err(R.reconstruct(0, 0, 2, Xnew), orc.interpret(codes[2:3], consts[2:3], Xnew)[0], 1.0) == 0.0
+    R.close()
+    if precision == gsgp.FP64:
+        # the whole run in step with the oracle from the same genomes
+        s2 = gsgp.Settings(pop_size=m, pool_size=r, genome_len=k, n_generations_max=G, seed=72)
+        R2 = _runner(s2, [d])
+        R2.eval_population(codes, consts)
+        S_tr, S_te = orc.interpret(codes[:m], consts[:m], d.X_train), orc.interpret(codes[:m], consts[:m], d.X_test)
+        sig_tr = orc.sigmoid(orc.interpret(codes[m:], consts[m:], d.X_train))
+        sig_te = orc.sigmoid(orc.interpret(codes[m:], consts[m:], d.X_test))
+        F, Ft = orc.rmse_rows(S_tr, d.y_train), orc.rmse_rows(S_te, d.y_test)
+        for g in range(1, G + 1):
+            rec = orc.select(cfg, g, F)
+            O_tr, O_te = orc.vary(rec, S_tr, sig_tr), orc.vary(rec, S_te, sig_te)
+            F_O, Ft_O = orc.rmse_rows(O_tr, d.y_train), orc.rmse_rows(O_te, d.y_test)
+            elite = orc.survive(F, Ft, F_O, Ft_O, S_tr, O_tr, S_te, O_te)
+            st = R2.generation(1)[0, 0]
+            assert records_equal(R2.records(0, g, 1)[0], rec), g
+            assert (st["elite_copied"], st["elite_src"], st["elite_dst"]) == tuple(elite), g
+            S_tr, S_te, F, Ft = O_tr, O_te, F_O, Ft_O
+            assert rel_err(R2.fitness(0)[0], F, 1e-300) <= 1e-12
+        R2.close()
+
+
+def test_philox_population_of_deep_programs_is_accepted():
+    """Gene probabilities that make most genomes deep (few functions): a
+    Philox-drawn population at k = 400 is accepted, its programs run in all
+    three interpreter passes, and free runs match the oracle."""
+    d = dataset(400, 100, 3, seed=74)
+    s = gsgp.Settings(pop_size=24, pool_size=12, genome_len=400, n_generations_max=3, seed=75,
+                      p_function=0.3, p_feature=0.6)
+    codes, _ = orc.genomes(oracle_config(s), 3, orc.TAG_POPULATION, 24)
+    depth = _stack_depths(codes)
+    assert depth.max() > 65 and (depth <= 7).sum() < len(depth)  # some beyond LDS, most beyond the first pass
+    _free_run_parity(s, d, 3)
+
+
+def test_semantics_cases_getter_matches_the_full_rows():
+    """Case-range inspection equals the same columns of the full semantics
+    for ranges inside the train cases, across the train/test boundary,
+    inside the test cases, and over everything (ragged sizes, FP32 and FP64,
+    population and pool)."""
+    d = dataset(2100, 333, 3, seed=76)
+    for prec in (gsgp.FP64, gsgp.FP32):
+        s = gsgp.Settings(pop_size=12, pool_size=7, n_generations_max=2, seed=77, precision=prec)
+        R = _runner(s, [d])
+        R.eval_population()
+        R.generation(2)
+        n_all = 2100 + 333
+        for which in (0, 1):
+            full = R.semantics(0, which)
+            for c0, n in ((0, 1), (5, 1100), (1020, 1030), (2000, 200), (2100, 333), (2431, 2), (0, n_all)):
+                assert np.array_equal(R.semantics_cases(0, which, c0, n), full[:, c0:c0 + n]), (prec, which, c0, n)
+        with pytest.raises(gsgp.GSGPError):
+            R.semantics_cases(0, 0, n_all - 1, 2)
+        R.close()
+
+
+def test_checkpoint_refuses_other_operator_settings():
+    """A checkpoint is refused (GSGP_ERR_ARG) by a handle whose operator
+    settings differ in any field that decides draws or values, and is taken
+    by a handle that differs only in launch and debug flags."""
+    import dataclasses
+    d = dataset(300, 80, 3, seed=78)
+    s = gsgp.Settings(pop_size=16, pool_size=8, n_generations_max=6, seed=79)
+    A = _runner(s, [d])
+    A.eval_population()
+    A.generation(2)
+    blob = A.checkpoint()
+    for change in (dict(tournament_size=5), dict(p_crossover=0.25), dict(mutation_step=0.2), dict(ms_random=1),
+                   dict(p_function=0.7), dict(p_feature=0.2), dict(erc_lo=-2.0), dict(erc_hi=0.5)):
+        B = _runner(dataclasses.replace(s, **change), [d])
+        with pytest.raises(gsgp.GSGPError) as e:
+            B.restore(blob)
+        assert e.value.status == -1, change
+        B.close()
+    C = _runner(dataclasses.replace(s, flags=gsgp.FLAG_NO_GRAPH), [d])
+    C.restore(blob)
+    C.generation(4)
+    A.generation(4)
+    assert np.array_equal(A.semantics(0, 0), C.semantics(0, 0))
+    A.close()
+    C.close()
