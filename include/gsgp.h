@@ -344,21 +344,23 @@ gsgp_status gsgp_checkpoint_size(gsgp_handle* h, size_t* bytes);
 
 /* Writes the checkpoint into h_buf (HOST, >= gsgp_checkpoint_size bytes):
  * the current population semantics and fitness, the squashed pool, the
- * genomes and their compiled form, the ancestry record so far (including
- * the next generation's draws) and the state words.  Every later draw is a
+ * genomes (the loading handle compiles them for its own workspace), the
+ * ancestry record so far (including the next generation's draws), the
+ * scaling table and target sums with local search, and the state words.  Every later draw is a
  * function of (seed, run, offspring, generation) and the fitness (Philox
  * counters), so a handle that loads it continues bit for bit.  Synchronises
  * the stream.  Errors: GSGP_ERR_ARG, GSGP_ERR_STATE, GSGP_ERR_HIP. */
 gsgp_status gsgp_checkpoint_save(gsgp_handle* h, void* h_buf, size_t bytes);
 
 /* Restores a checkpoint into a handle made with the same configuration
- * (sizes, generations, precision, seed) on data of the same shapes (the data
- * itself is the caller's); the handle is then at the saved generation, as if
- * gsgp_eval_population and those generations had run.  A later
- * gsgp_eval_population restarts from generation 0.
+ * (sizes, generations, precision, seed, every operator setting and the
+ * local-search flag; launch and debug flags may differ) on data of the same
+ * shapes (the data itself is the caller's); the handle is then at the saved
+ * generation, as if gsgp_eval_population and those generations had run.  A
+ * later gsgp_eval_population restarts from generation 0.
  * Errors: GSGP_ERR_ARG (not a checkpoint, other configuration, truncated,
- * or written by a version of the library with another compiled-genome
- * format), GSGP_ERR_STATE, GSGP_ERR_HIP. */
+ * or written by another checkpoint version of the library), GSGP_ERR_STATE,
+ * GSGP_ERR_HIP. */
 gsgp_status gsgp_checkpoint_load(gsgp_handle* h, const void* h_buf, size_t bytes);
 
 /* Byte offsets (within the workspace) of the guards that GSGP_FLAG_GUARDS

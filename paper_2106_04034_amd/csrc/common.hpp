@@ -35,10 +35,12 @@ constexpr int kSpillWaves = 128;
 // Stack values below the top two that a genome of k genes can need: its
 // deepest stack up to its last valid function is at most k - 1 values.
 constexpr int64_t max_need(int64_t k) { return k > 3 ? k - 3 : 0; }
-// Programs whose LDS stack needs at most this many values per lane run in
-// the first interpreter pass with a small LDS column per wave (8 waves per
-// SIMD); the few deeper ones run in a second pass sized for the deepest.
-constexpr int kShallowSlots = 5;
+// Programs whose stack needs more than this many LDS values per lane form a
+// run's deep list (the later interpreter passes read it); the first pass
+// takes every program within it with a small LDS column per wave.
+constexpr int kShallowSlots = 2;
+// LDS column of the second (wide) pass over the deep list.
+constexpr int kWideDeepSlots = 6;
 // The interpreter reads a program's ops eight at a time; the compiled-op
 // buffers carry this many entries of padding after the last program.
 constexpr int kOpPad = 8;
@@ -103,6 +105,7 @@ struct RunDev {
   int32_t pad0;
   int64_t vary_task0;       // first task of this run in the variation launch
   int64_t cblk0;            // first 128-case block of this run (interpreter)
+  int64_t cblk0w;           // first 256-case block of this run (wide interpreter)
   int64_t col0;             // first padded column of this run (data prep)
 };
 
@@ -175,11 +178,16 @@ hipError_t launch_set_state(const RunDev* d_runs, int32_t n_runs, int32_t word, 
                             hipStream_t s);
 hipError_t launch_genome(const RunDev* d_runs, const Params& p, hipStream_t s);
 hipError_t launch_compile(const RunDev* d_runs, const Params& p, hipStream_t s);
-// slots: stack values per lane kept in LDS (at least 1).  deep_max < 0: the
-// first pass, every program whose need fits in `slots`; deep_max >= 0: the
-// second pass over each run's deep list, at most deep_max programs per run.
-hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_blocks, int slots,
+// Interpreter passes: each takes the programs with lo < need <= slots,
+// from every program (deep_max < 0) or from each run's deep list (at most
+// deep_max programs per run).  launch_interpret: two cases per lane, any
+// slots up to kMaxLdsSlots; launch_interpret_wide: four cases per lane,
+// slots kShallowSlots or kWideDeepSlots, for runs whose rows of X are
+// shorter than 4 GiB.
+hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_blocks, int lo, int slots,
                             int32_t deep_max, hipStream_t s);
+hipError_t launch_interpret_wide(const RunDev* d_runs, const Params& p, int64_t case_blocks, int lo, int slots,
+                                 int32_t deep_max, hipStream_t s);
 // Third pass: every program on a deep list whose need exceeds kMaxLdsSlots,
 // with its stack in `spill` (kSpillWaves columns of slots x 2 x 64 doubles).
 hipError_t launch_interpret_spill(const RunDev* d_runs, const Params& p, double* spill, int slots,

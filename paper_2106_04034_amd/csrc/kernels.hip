@@ -238,8 +238,8 @@ __global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs
     if (c >= 0) {
       prev = (kClsPush << 2) | kPushFeature | dfield | (c << 16);
       ops[n] = prev;
-      // the feature's row offset in this run's X, bit for bit (see eval_program)
-      opv[n] = __longlong_as_double((long long)c * R.ld);
+      // the address of the feature's row in this run's X, bit for bit (see eval_program)
+      opv[n] = __longlong_as_double((long long)(R.X + (int64_t)c * R.ld));
       ++n;
       ++depth;
     } else if (c == -5) {
@@ -312,11 +312,12 @@ __device__ __forceinline__ void eval_program(const int32_t* ops, const double* o
 #pragma unroll
   for (int v = 0; v < V; ++v) at[v] = ok[v] ? col[v] : ld - 1;
   auto feature = [&](int w, double c, double (&x)[V]) {
-    // BAKED: the compile step stored the row offset f * ld of the handle's
-    // own X in the op's constant slot (an integer's bits, never used as a
-    // number); other callers pass an X of their own and use the index
-    const int64_t row = BAKED ? (int64_t)__double_as_longlong(c) : (int64_t)((uint32_t)w >> 16) * ld;
-    const GSGP_GLOBAL double* xg = (const GSGP_GLOBAL double*)X + row;
+    // BAKED: the compile step stored the address of the feature's row in the
+    // handle's own X in the op's constant slot (a pointer's bits, never used
+    // as a number); other callers pass an X of their own and use the index
+    const GSGP_GLOBAL double* xg =
+        BAKED ? (const GSGP_GLOBAL double*)__double_as_longlong(c)
+              : (const GSGP_GLOBAL double*)X + (int64_t)((uint32_t)w >> 16) * ld;
 #pragma unroll
     for (int v = 0; v < V; ++v) x[v] = xg[at[v]];
   };
@@ -412,6 +413,119 @@ __device__ __forceinline__ void eval_program(const int32_t* ops, const double* o
   for (int v = 0; v < V; ++v) out[v] = tos[v];
 }
 
+// The first interpreter passes: eval_program for V cases per lane with the
+// stack's LDS column bounded at compile time, written to keep the scalar
+// work per op small (the kernel is bound by the scalar unit's issue rate:
+// every op is decoded and dispatched by wave-uniform branches).
+//   - Dispatch tests single bits of the op word: bit 3 a function applied
+//     to the top of the stack and a terminal (fused op), else bit 2 a
+//     function of the top two values, else a push; bit 1 multiplication or
+//     division, bit 0 subtraction or division (or, for a push, a constant).
+//   - A feature op's constant slot holds the absolute address of its row of
+//     the run's X; each lane adds a fixed 32-bit byte offset (its case), so
+//     a feature load needs no address arithmetic at all.
+//   - Both function forms share one `apply` (tos = f(tos, b)): a function of
+//     the top two values first moves them into place.
+// The FP64 operations and their order are those of eval_program, so results
+// are the same bits.
+template <int V, typename Stack>
+__device__ __forceinline__ void eval_program_wide(const int32_t* ops, const double* opv, int n,
+                                                  const uint32_t (&off)[V], Stack stk, int lane, double (&out)[V]) {
+  constexpr int kBatch = kOpPad;
+  const GSGP_CONST int32_t* cops = (const GSGP_CONST int32_t*)ops;
+  const GSGP_CONST double* copv = (const GSGP_CONST double*)opv;
+  double tos[V], nos[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    tos[v] = 0.0;
+    nos[v] = 0.0;
+  }
+  auto feature = [&](double c, double (&x)[V]) {
+    const GSGP_GLOBAL char* row = (const GSGP_GLOBAL char*)__double_as_longlong(c);
+#pragma unroll
+    for (int v = 0; v < V; ++v) x[v] = *(const GSGP_GLOBAL double*)(row + off[v]);
+  };
+  auto clamp = [](double x) { return fmin(fmax(x, -kFltMax), kFltMax); };
+  auto apply = [&](int w, const double (&b)[V]) {
+    if (w & 2) {
+      if (w & 1) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const bool tiny = fabs(b[v]) < 1e-6;  // protected division, as in eval_program
+          const double q = tos[v] / (tiny ? 1.0 : b[v]);
+          tos[v] = clamp(tiny ? 1.0 : q);
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) tos[v] = clamp(tos[v] * b[v]);
+      }
+    } else {
+      if (w & 1) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) tos[v] = clamp(tos[v] - b[v]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) tos[v] = clamp(tos[v] + b[v]);
+      }
+    }
+  };
+  for (int j0 = 0; j0 < n; j0 += kBatch) {
+    int wv[kBatch];
+    double cv[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      // one batch per two scalar loads; reads past a program's end stay
+      // inside the buffers' padding and are never used
+      wv[u] = cops[j0 + u];
+      cv[u] = copv[j0 + u];
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      if (j0 + u >= n) break;
+      const int w = wv[u];
+      if (w & 8) {  // fused: tos = f(tos, terminal)
+        double b[V];
+        if (w & 4) {
+#pragma unroll
+          for (int v = 0; v < V; ++v) b[v] = cv[u];
+        } else {
+          feature(cv[u], b);
+        }
+        apply(w, b);
+      } else if (w & 4) {  // tos = f(nos, tos), then the new nos from LDS
+        double b[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          b[v] = tos[v];
+          tos[v] = nos[v];
+        }
+        apply(w, b);
+        const int d = (w >> 4) & kOpDepthMax;
+        if (d >= 3) {
+#pragma unroll
+          for (int v = 0; v < V; ++v) nos[v] = stk[((d - 3) * V + v) * kWave + lane];
+        }
+      } else {  // push: nos to LDS, tos to nos, the terminal to tos
+        const int d = (w >> 4) & kOpDepthMax;
+        if (d >= 2) {
+#pragma unroll
+          for (int v = 0; v < V; ++v) stk[((d - 2) * V + v) * kWave + lane] = nos[v];
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) nos[v] = tos[v];
+        if (w & 1) {
+#pragma unroll
+          for (int v = 0; v < V; ++v) tos[v] = cv[u];
+        } else {
+          feature(cv[u], tos);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < V; ++v) out[v] = tos[v];
+}
+
 constexpr int kInterpV = 2;              // cases per lane
 constexpr int kInterpTile = kWave * kInterpV;  // cases per block
 static_assert(kInterpTile == kInterpCases, "the runtime plans kInterpCases-case blocks");
@@ -426,16 +540,15 @@ constexpr int kInterpProgsPerWave = 1;
 // Writes one program's values for one case block: population rows as they
 // are, pool rows squashed by the logistic function (the random functions R_u
 // of GSM, Section 2); padding columns as exact zeros.
-template <typename T>
-__device__ __forceinline__ void store_program(const RunDev& R, const Params& p, int prog,
-                                              const int64_t (&col)[kInterpV], const bool (&ok)[kInterpV],
-                                              const double (&out)[kInterpV]) {
+template <typename T, int V>
+__device__ __forceinline__ void store_program(const RunDev& R, const Params& p, int prog, const int64_t (&col)[V],
+                                              const bool (&ok)[V], const double (&out)[V]) {
   const bool pool = prog >= p.m;
   T* dst = pool ? (T*)R.sigR : (T*)R.S[0];
   const int64_t nrows = pool ? p.r : p.m;
   const int64_t row = pool ? prog - p.m : prog;
 #pragma unroll
-  for (int v = 0; v < kInterpV; ++v) {
+  for (int v = 0; v < V; ++v) {
     if (!ok[v]) continue;
     const int64_t c = col[v];
     const bool real = c < R.n_train || (c >= R.tr_pad && c < R.tr_pad + R.n_test);
@@ -458,7 +571,7 @@ __device__ __forceinline__ void store_program(const RunDev& R, const Params& p, 
 // number of resident waves more than it saved in L2 reads.)
 template <typename T>
 __global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ runs, Params p, int32_t pgroups,
-                                                   int slots, int deep_pass) {
+                                                   int lo, int slots, int deep_pass) {
   extern __shared__ double lds[];
   const int lane = threadIdx.x & 63;
   const int wave = uni(threadIdx.x >> 6);
@@ -488,13 +601,63 @@ __global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ ru
       if (idx >= rows) break;
       prog = idx;
     }
-    // programs deeper than this pass's column are left to a later pass
-    if (uni(cload(&R.need[prog])) > slots) continue;
+    // this pass takes the programs with lo < need <= slots
+    const int need = uni(cload(&R.need[prog]));
+    if (need <= lo || need > slots) continue;
     double out[kInterpV];
     eval_program<kInterpV, true>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k, uni(cload(&R.nops[prog])),
                                  R.X, ld, col, ok, (LdsStack)stk, lane, out);
-    store_program<T>(R, p, prog, col, ok, out);
+    store_program<T, kInterpV>(R, p, prog, col, ok, out);
   }
+}
+
+// ComputeSemantics with eval_program_wide: a block of 4 waves takes one
+// block of kWideTile cases of one run (lanes own kWideV cases each) and
+// 4 programs, one per wave; a wave's LDS column holds SLOTS stack values per
+// lane.  The pass takes the programs with lo < need <= SLOTS, from all
+// programs or (deep_pass) from the run's deep list.  Every lane's byte
+// offset into a feature row (its case, or the last column for lanes past
+// it, whose values are never stored) fits in 32 bits: the runtime uses this
+// kernel only when every run's rows are shorter than 4 GiB.
+constexpr int kWideV = 4;
+constexpr int kWideTile = kWave * kWideV;
+constexpr int kWideWaves = 4;
+
+template <typename T, int SLOTS>
+__global__ __launch_bounds__(kWideWaves * kWave) void k_interpret_wide(const RunDev* __restrict__ runs, Params p,
+                                                                        int32_t pgroups, int lo, int deep_pass) {
+  __shared__ double lds[kWideWaves * SLOTS * kWideV * kWave];
+  const int lane = threadIdx.x & 63;
+  const int wave = uni(threadIdx.x >> 6);
+  const int64_t cbg = blockIdx.x / pgroups;  // case block over all runs
+  const int pg = (int)(blockIdx.x - cbg * pgroups);
+  const int run = find_run(p.n_runs, cbg, [&](int r) { return runs[r].cblk0w; });
+  const RunDev& R = runs[run];
+  const int64_t cb = cbg - R.cblk0w;
+  const int idx = pg * kWideWaves + wave;
+  int prog;
+  if (deep_pass) {
+    if (idx >= uni(cload(&R.state[kStDeepCount]))) return;
+    prog = uni(cload(&R.deep[idx]));
+  } else {
+    if (idx >= p.m + p.r) return;
+    prog = idx;
+  }
+  const int need = uni(cload(&R.need[prog]));
+  if (need <= lo || need > SLOTS) return;
+  int64_t col[kWideV];
+  bool ok[kWideV];
+  uint32_t off[kWideV];
+#pragma unroll
+  for (int v = 0; v < kWideV; ++v) {
+    col[v] = cb * kWideTile + v * kWave + lane;
+    ok[v] = col[v] < R.ld;
+    off[v] = (uint32_t)((ok[v] ? col[v] : R.ld - 1) * (int64_t)sizeof(double));
+  }
+  double out[kWideV];
+  eval_program_wide<kWideV>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k, uni(cload(&R.nops[prog])),
+                            off, (LdsStack)(lds + wave * SLOTS * kWideV * kWave), lane, out);
+  store_program<T, kWideV>(R, p, prog, col, ok, out);
 }
 
 // Third pass: the deep-list programs whose stack exceeds the largest LDS
@@ -529,7 +692,7 @@ __global__ __launch_bounds__(64) void k_interpret_spill(const RunDev* __restrict
       double out[kInterpV];
       eval_program<kInterpV, true>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k,
                                    uni(cload(&R.nops[prog])), R.X, R.ld, col, ok, (GlobalStack)stk, lane, out);
-      store_program<T>(R, p, prog, col, ok, out);
+      store_program<T, kInterpV>(R, p, prog, col, ok, out);
     }
   }
 }
@@ -1516,7 +1679,7 @@ hipError_t launch_compile(const RunDev* d_runs, const Params& p, hipStream_t s) 
   return hipGetLastError();
 }
 
-hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_blocks, int slots,
+hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_blocks, int lo, int slots,
                             int32_t deep_max, hipStream_t s) {
   if (slots < 1) slots = 1;
   if (slots > kMaxLdsSlots) return hipErrorInvalidValue;  // deeper stacks take the spill pass
@@ -1531,9 +1694,39 @@ hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_
   const dim3 grid((unsigned)(case_blocks * pgroups)), block(waves * kWave);
   const int deep_pass = deep_max > 0 ? 1 : 0;
   if (p.precision == GSGP_FP64)
-    hipLaunchKernelGGL((k_interpret<double>), grid, block, shmem, s, d_runs, p, pgroups, slots, deep_pass);
+    hipLaunchKernelGGL((k_interpret<double>), grid, block, shmem, s, d_runs, p, pgroups, lo, slots, deep_pass);
   else
-    hipLaunchKernelGGL((k_interpret<float>), grid, block, shmem, s, d_runs, p, pgroups, slots, deep_pass);
+    hipLaunchKernelGGL((k_interpret<float>), grid, block, shmem, s, d_runs, p, pgroups, lo, slots, deep_pass);
+  return hipGetLastError();
+}
+
+template <typename T, int SLOTS>
+void launch_wide_as(const RunDev* d_runs, const Params& p, dim3 grid, int32_t pgroups, int lo, int deep_pass,
+                    hipStream_t s) {
+  hipLaunchKernelGGL((k_interpret_wide<T, SLOTS>), grid, dim3(kWideWaves * kWave), 0, s, d_runs, p, pgroups, lo,
+                     deep_pass);
+}
+
+hipError_t launch_interpret_wide(const RunDev* d_runs, const Params& p, int64_t case_blocks, int lo, int slots,
+                                 int32_t deep_max, hipStream_t s) {
+  if (deep_max == 0) return hipSuccess;
+  if (slots != kShallowSlots && slots != kWideDeepSlots) return hipErrorInvalidValue;
+  const int progs = deep_max > 0 ? deep_max : p.m + p.r;
+  const int32_t pgroups = (progs + kWideWaves - 1) / kWideWaves;
+  if (case_blocks * pgroups > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  const dim3 grid((unsigned)(case_blocks * pgroups));
+  const int deep_pass = deep_max > 0 ? 1 : 0;
+  if (p.precision == GSGP_FP64) {
+    if (slots == kShallowSlots)
+      launch_wide_as<double, kShallowSlots>(d_runs, p, grid, pgroups, lo, deep_pass, s);
+    else
+      launch_wide_as<double, kWideDeepSlots>(d_runs, p, grid, pgroups, lo, deep_pass, s);
+  } else {
+    if (slots == kShallowSlots)
+      launch_wide_as<float, kShallowSlots>(d_runs, p, grid, pgroups, lo, deep_pass, s);
+    else
+      launch_wide_as<float, kWideDeepSlots>(d_runs, p, grid, pgroups, lo, deep_pass, s);
+  }
   return hipGetLastError();
 }
 

@@ -196,6 +196,8 @@ struct gsgp_handle {
   Params params;
   VaryLaunch vary{}, rows{};
   int64_t interp_tasks = 0;  // interpreter case blocks over all runs
+  int64_t interp_tasks_w = 0;  // wide interpreter case blocks over all runs
+  bool interp_wide = false;    // every run's rows of X are shorter than 4 GiB
   int32_t surv_blocks = 0;
   int32_t slots = 1;         // interpreter stack values per lane in LDS
   int32_t max_blocks = 0;
@@ -490,7 +492,8 @@ gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_ru
   h->runs_d = (RunDev*)(ws + plan.runs_dev);
   int32_t* state = (int32_t*)(ws + plan.state);
   h->runs_h.resize(n_runs);
-  int64_t col = 0, itask = 0;
+  int64_t col = 0, itask = 0, itask_w = 0;
+  bool wide_ok = true;
   int32_t sblk = 0;
   for (int32_t i = 0; i < n_runs; ++i) {
     const RunPlan& q = plan.runs[i];
@@ -533,6 +536,9 @@ gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_ru
     col += q.ld;
     R.cblk0 = itask;
     itask += (q.ld + kInterpCases - 1) / kInterpCases;
+    R.cblk0w = itask_w;
+    itask_w += (q.ld + 4 * kWave - 1) / (4 * kWave);
+    wide_ok = wide_ok && (uint64_t)q.ld * sizeof(double) < ((uint64_t)1 << 32);
     R.surv_blk0 = sblk;
     // survival blocks per run: each copies about 16 KiB of an elite row
     const int64_t nb = ((int64_t)storage_bytes(cfg->precision) * q.ld + 16383) / 16384;
@@ -540,6 +546,8 @@ gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_ru
     sblk += R.surv_blks;
   }
   h->interp_tasks = itask;
+  h->interp_tasks_w = itask_w;
+  h->interp_wide = wide_ok;
   h->surv_blocks = sblk;
   plan_vary(h, 4, 16, 1, 0);
   plan_rows(h);
@@ -598,6 +606,33 @@ gsgp_status gsgp_destroy(gsgp_handle* h) {
 
 namespace {
 
+// ComputeSemantics of every compiled program, in passes by the stack depth
+// a program needs (h->slots is the deepest): every program that fits a
+// small LDS column, then the deep list in larger columns, then the programs
+// beyond any LDS column (spill stacks).  Runs whose rows of X are shorter
+// than 4 GiB (all practical ones) use the four-cases-per-lane kernel for the
+// first two passes.
+hipError_t interpret_all(gsgp_handle* h, int32_t deep_max, hipStream_t s) {
+  const Params& p = h->params;
+  hipError_t e;
+  int done;  // programs with need <= done are evaluated
+  if (h->interp_wide) {
+    e = launch_interpret_wide(h->runs_d, p, h->interp_tasks_w, -1, kShallowSlots, -1, s);
+    if (e == hipSuccess && h->slots > kShallowSlots)
+      e = launch_interpret_wide(h->runs_d, p, h->interp_tasks_w, kShallowSlots, kWideDeepSlots, deep_max, s);
+    done = kWideDeepSlots;
+  } else {
+    constexpr int kFirst = 5;  // the two-cases-per-lane kernel's first column
+    e = launch_interpret(h->runs_d, p, h->interp_tasks, -1, std::min(h->slots, kFirst), -1, s);
+    done = kFirst;
+  }
+  if (e == hipSuccess && h->slots > done)
+    e = launch_interpret(h->runs_d, p, h->interp_tasks, done, std::min(h->slots, kMaxLdsSlots), deep_max, s);
+  if (e == hipSuccess && h->slots > kMaxLdsSlots)
+    e = launch_interpret_spill(h->runs_d, p, (double*)(h->ws + h->plan.spill), h->slots, s);
+  return e;
+}
+
 // Algorithm 1 before the loop.  ev (nullable) receives four events: start,
 // after the genomes, after the semantics (compile + interpret), and after
 // the initial fitness and first draws.
@@ -645,13 +680,8 @@ gsgp_status eval_impl(gsgp_handle* h, const int32_t* h_codes, const double* h_co
     h->poisoned = true;
     return fail(GSGP_ERR_STATE, "compiled stack depth %d exceeds the bound for genomes of %d genes", deepest, p.k);
   }
-  // every program that fits a small LDS column, then the deeper ones in an
-  // LDS column sized for them, then those beyond any LDS column
-  HIPCHK(h, launch_interpret(h->runs_d, p, h->interp_tasks, std::min(h->slots, kShallowSlots), -1, h->stream));
-  if (h->slots > kShallowSlots)
-    HIPCHK(h, launch_interpret(h->runs_d, p, h->interp_tasks, std::min(h->slots, kMaxLdsSlots), deep_max, h->stream));
-  if (h->slots > kMaxLdsSlots)
-    HIPCHK(h, launch_interpret_spill(h->runs_d, p, (double*)(h->ws + h->plan.spill), h->slots, h->stream));
+  HIPCHK(h, interpret_all(h, deep_max, h->stream));
+
   if (ev) HIPCHK(h, hipEventRecord(ev[2], h->stream));
   if (p.ls) HIPCHK(h, launch_target_sums(h->runs_d, p, h->stream));  // and generation 0's scaling
   HIPCHK(h, launch_vary(h->runs_d, p, h->rows, true, h->stream));
@@ -1226,22 +1256,32 @@ gsgp_status gsgp_export_linear(gsgp_handle* h, int32_t run, int32_t gen, int32_t
   return GSGP_OK;
 }
 
-gsgp_status gsgp_reconstruct(gsgp_handle* h, int32_t run, int32_t gen, int32_t individual, const double* d_X,
-                             int64_t n, double* d_out, void* d_scratch, size_t scratch_bytes) {
+}  // extern "C"
+
+namespace {
+
+gsgp_status check_reconstruct_args(gsgp_handle* h, int32_t run, int32_t gen, int32_t individual, const double* d_X,
+                                   int64_t n, double* d_out) {
   gsgp_status st = check_run(h, run);
   if (st != GSGP_OK) return st;
   if (gen < 0 || gen > h->gen) return fail(GSGP_ERR_ARG, "generation %d not in [0, %d]", gen, h->gen);
   if (individual < 0 || individual >= h->cfg.pop_size) return fail(GSGP_ERR_ARG, "individual out of range");
   if (n < 1 || n > ((int64_t)1 << 40)) return fail(GSGP_ERR_ARG, "n must be >= 1");
   if (!d_X || !d_out) return fail(GSGP_ERR_ARG, "NULL data or output pointer");
-  if (!d_scratch || ((uintptr_t)d_scratch) % kAlign) return fail(GSGP_ERR_WORKSPACE, "scratch must be non-NULL and 256-byte aligned");
+  return GSGP_OK;
+}
+
+// Lineage reconstruction into `scratch_bytes` of device scratch at `sc`;
+// `whose` names it in errors.
+gsgp_status reconstruct_with(gsgp_handle* h, int32_t run, int32_t gen, int32_t individual, const double* d_X,
+                             int64_t n, double* d_out, char* sc, size_t scratch_bytes, const char* whose) {
   Lineage L;
-  st = walk_lineage(h, run, gen, individual, n, &L);
+  gsgp_status st = walk_lineage(h, run, gen, individual, n, &L);
   if (st != GSGP_OK) return st;
-  if (scratch_bytes < L.total) return fail(GSGP_ERR_WORKSPACE, "scratch has %zu bytes, needs %zu", scratch_bytes, L.total);
+  if (scratch_bytes < L.total)
+    return fail(GSGP_ERR_WORKSPACE, "%s has %zu bytes, this reconstruction needs %zu", whose, scratch_bytes, L.total);
   const RunDev& R = h->runs_h[run];
   const int32_t m = h->cfg.pop_size;
-  char* sc = (char*)d_scratch;
   double* Xfm = (double*)(sc + L.off_X);
   double* pool = (double*)(sc + L.off_pool);
   double* bufA = (double*)(sc + L.off_A);
@@ -1332,6 +1372,19 @@ gsgp_status gsgp_reconstruct(gsgp_handle* h, int32_t run, int32_t gen, int32_t i
   return GSGP_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+gsgp_status gsgp_reconstruct(gsgp_handle* h, int32_t run, int32_t gen, int32_t individual, const double* d_X,
+                             int64_t n, double* d_out, void* d_scratch, size_t scratch_bytes) {
+  gsgp_status st = check_reconstruct_args(h, run, gen, individual, d_X, n, d_out);
+  if (st != GSGP_OK) return st;
+  if (!d_scratch || ((uintptr_t)d_scratch) % kAlign) return fail(GSGP_ERR_WORKSPACE, "scratch must be non-NULL and 256-byte aligned");
+  return reconstruct_with(h, run, gen, individual, d_X, n, d_out, (char*)d_scratch, scratch_bytes, "the scratch");
+}
+
+
 
 // The entry points that launch kernels check the workspace guards
 // (GSGP_FLAG_GUARDS) before returning.
@@ -1378,7 +1431,7 @@ struct CkptHeader {
   uint32_t seed, result_flags;
   double p_crossover, mutation_step, p_function, p_feature, erc_lo, erc_hi;
 };
-constexpr int32_t kCkptVersion = 4;  // 4: every operator setting in the header
+constexpr int32_t kCkptVersion = 5;  // 5: genomes recompiled on load
 static_assert(sizeof(CkptHeader) == 112, "no padding between header fields");
 
 struct CkptPiece {
@@ -1402,11 +1455,10 @@ std::vector<CkptPiece> ckpt_pieces(const gsgp_handle* h) {
     out.push_back({cur ? q.Ft1 : q.Ft0, 8 * (size_t)m});
     out.push_back({q.rec, sizeof(gsgp_record) * (size_t)(n_rec * m)});
     out.push_back({q.stats, sizeof(gsgp_gen_stats) * (size_t)(h->gen + 1)});
+    // the genomes; their compiled form holds addresses in this workspace
+    // and is rebuilt by the loading handle
     out.push_back({q.code, 4 * (size_t)((m + r) * k)});
     out.push_back({q.cval, 8 * (size_t)((m + r) * k)});
-    out.push_back({q.ops, 4 * (size_t)((m + r) * k)});
-    out.push_back({q.opv, 8 * (size_t)((m + r) * k)});
-    out.push_back({q.nops, 4 * (size_t)(m + r)});
     if (h->cfg.flags & GSGP_FLAG_LOCAL_SEARCH) {
       out.push_back({q.ls, sizeof(double) * 2 * (size_t)(m * (h->gen + 1))});
       out.push_back({q.tsum, sizeof(double) * 4});
@@ -1526,8 +1578,21 @@ gsgp_status gsgp_checkpoint_load(gsgp_handle* h, const void* h_buf, size_t bytes
     HIPCHK(h, hipMemcpy(h->ws + p.off, in, p.bytes, hipMemcpyHostToDevice));
     in += p.bytes;
   }
+  // compile the loaded genomes for this workspace (the depth words restart)
+  HIPCHK(h, launch_set_state(h->runs_d, h->n_runs, kStMaxDepth, 0, h->stream));
+  HIPCHK(h, launch_set_state(h->runs_d, h->n_runs, kStDeepCount, 0, h->stream));
+  HIPCHK(h, launch_compile(h->runs_d, h->params, h->stream));
+  int32_t* state = (int32_t*)(h->ws + h->plan.state);
+  HIPCHK(h, hipMemcpyAsync(h->pinned, state, sizeof(int32_t) * kStWords * h->n_runs, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  int32_t deepest = 0;
+  for (int32_t r = 0; r < h->n_runs; ++r) deepest = std::max(deepest, h->pinned[kStWords * r + kStMaxDepth]);
   h->gen = c.gen;
-  h->slots = c.slots;
+  h->slots = std::max(1, deepest - 2);
+  if (h->slots != c.slots) {
+    h->poisoned = true;
+    return fail(GSGP_ERR_STATE, "the loaded genomes compile to another stack depth (%d, saved %d)", h->slots, c.slots);
+  }
   h->evaluated = true;
   return check_guards(h, GSGP_OK);
 }

@@ -19,9 +19,10 @@ near ties, whose relative fitness gap is bounded and reported).
   - large_fp32_1m (1,000,000 / 250,000 cases, 64 features, m = r = 2,048,
     FP32): 20 generations on the device at full size; the oracle (61 GB in
     FP64 for every case) follows the lineage on a fixed slice of the cases
-    (the first 1/8 of the train and of the test cases): every element of the
-    slice within 1e-4 * max(|oracle|, RMS(t)), and the slice RMSE of every
-    individual within 1e-4 relative;
+    (the first 1/8 of the train and of the test cases): the slice RMSE of
+    every individual within 1e-4 relative, and every element of the slice
+    within 1e-4 * max(|oracle|, RMS(t), RMS of the individual's row) (FP32
+    rounding of operands that cancel, see _slice_check);
   - precision_1m (large_fp32_1m data, m = r = 1,024): the FP64 replay of an
     FP32-Kahan lineage, which the precision benchmark uses as its drift
     reference, against the oracle for the first 50 generations on a 1/16
@@ -159,15 +160,27 @@ def _slice(d, frac):
     return ntr, nte, (d.X_train[:ntr], d.y_train[:ntr], d.X_test[:nte], d.y_test[:nte])
 
 
-def _slice_check(R, d, ntr, nte, tol, worst):
-    """Compares the device's population on the case slice with the oracle's."""
+def _slice_check(R, d, ntr, nte, tol, worst, row_scale=False):
+    """Compares the device's population on the case slice with the oracle's.
+    Element errors are relative to max(|oracle|, RMS(t)); with row_scale
+    (FP32 storage) also to the RMS of the individual's own row, because a
+    crossover of two large rows that nearly cancel at a case keeps the FP32
+    rounding of its operands (about u times their magnitude), however small
+    the result there."""
     n_train = d.X_train.shape[0]
     floor = float(np.sqrt(np.mean(d.y_train[:ntr] ** 2)))
+
+    def scale(b):
+        f = np.maximum(np.abs(b), floor)
+        if row_scale:
+            f = np.maximum(f, np.sqrt(np.mean(b ** 2, axis=1))[:, None])
+        return f
 
     def check(g, S_tr, S_te, F, Ft):
         A = R.semantics_cases(0, 0, 0, ntr)
         B = R.semantics_cases(0, 0, n_train, nte)
-        worst["sem"] = max(worst["sem"], _rel(A, S_tr, floor), _rel(B, S_te, floor))
+        worst["sem"] = max(worst["sem"], float(np.max(np.abs(A - S_tr) / scale(S_tr))),
+                           float(np.max(np.abs(B - S_te) / scale(S_te))))
         f_tr = np.sqrt(np.mean((A - d.y_train[:ntr]) ** 2, axis=1))
         f_te = np.sqrt(np.mean((B - d.y_test[:nte]) ** 2, axis=1))
         worst["fit"] = max(worst["fit"], _rel(f_tr, F, 1e-300), _rel(f_te, Ft, 1e-300))
@@ -187,7 +200,8 @@ def test_large_fp32_1m_drift_on_a_case_slice():
     R.eval_population()
     ntr, nte, data = _slice(d, 8)
     worst = {"sem": 0.0, "fit": 0.0}
-    res = orc.run(oracle_config(s), *data, G, drive=_Lineage(R).pair(), on_generation=_slice_check(R, d, ntr, nte, 1e-4, worst))
+    res = orc.run(oracle_config(s), *data, G, drive=_Lineage(R).pair(),
+                  on_generation=_slice_check(R, d, ntr, nte, 1e-4, worst, row_scale=True))
     # the oracle's own decisions use the slice's fitness, so its replay check
     # is informative only: the draws themselves must still match
     assert all(c["draw_mismatch"] == 0 for c in res.replay)
