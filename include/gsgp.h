@@ -15,7 +15,9 @@
  *    changes no state.
  *  - Device memory is owned by the caller.  The library never calls
  *    hipMalloc/hipFree; it carves the caller's workspace.  The handle owns
- *    only host memory and a HIP graph cache.
+ *    only host memory and a HIP graph cache.  The one device array of the
+ *    library's own is the static scratch of gsgp_reconstruct_static
+ *    (GSGP_STATIC_SCRATCH_BYTES on each GPU it runs on).
  *  - All device work is enqueued on the HIP stream given to gsgp_init (NULL
  *    is the legacy default stream).  Calls that return host data (getters,
  *    h_stats != NULL) synchronise that stream.  A handle is not thread safe.
@@ -217,6 +219,29 @@ gsgp_status gsgp_reconstruct_scratch_size(gsgp_handle* h, int32_t run, int32_t g
 gsgp_status gsgp_reconstruct(gsgp_handle* h, int32_t run, int32_t gen, int32_t individual,
                              const double* d_X, int64_t n, double* d_out, void* d_scratch,
                              size_t scratch_bytes);
+
+/* Bytes of the device scratch array that gsgp_reconstruct_static uses on
+ * each GPU (64 MiB). */
+#define GSGP_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * reconstruction as gsgp_reconstruct, with its scratch taken from an array
+ * of GSGP_STATIC_SCRATCH_BYTES that the library keeps on each GPU it runs on
+ * for the life of the process, instead of caller scratch.  The caller still
+ * passes d_X and d_out (DEVICE).  The call makes no device allocation.  A
+ * reconstruction that needs more scratch than the array holds (see
+ * gsgp_reconstruct_scratch_size) is refused with GSGP_ERR_WORKSPACE before
+ * any device work.  All calls on one GPU share its array, which keeps the
+ * last call's contents (every byte a call reads it has written first): the
+ * library serialises such calls within a process with a lock, and the call
+ * returns only after its work is done (it synchronises the stream).  Work on
+ * other streams that overlapped one of these calls could not touch the
+ * array, which is internal to the library.
+ * Errors: as gsgp_reconstruct; GSGP_ERR_UNSUPPORTED for a device index
+ * beyond 63. */
+gsgp_status gsgp_reconstruct_static(gsgp_handle* h, int32_t run, int32_t gen, int32_t individual,
+                                    const double* d_X, int64_t n, double* d_out);
 
 /* Compact model of a mutation-only lineage (the paper's own loop; GSM,
  * Section 2, and the lineage structures of Section 2.1 stage 3): individual

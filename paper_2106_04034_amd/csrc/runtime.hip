@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <set>
 #include <string>
 #include <vector>
@@ -21,7 +22,34 @@
 
 using namespace gsgp;
 
+// Device scratch of gsgp_reconstruct_static, for callers that cannot
+// allocate: one copy of this array on every GPU the library runs on, held
+// until the process ends.  Host code never uses the array's name as an
+// address; it uses the per-device address that hipGetSymbolAddress returns.
+constexpr size_t kStaticScratchBytes = GSGP_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+struct StaticScratch {
+  std::mutex call;       // one reconstruction at a time on this device
+  char* ptr = nullptr;   // device address of `scratch` on this device
+};
+StaticScratch g_static[kMaxDevices];
+std::mutex g_static_setup;
+
+// Resolves the device's copy of `scratch` once, with that device current.
+hipError_t resolve_static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipSuccess;  // the static entry point refuses such devices
+  std::lock_guard<std::mutex> lock(g_static_setup);
+  if (g_static[device].ptr) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_static[device].ptr = (char*)p;
+  return hipSuccess;
+}
 
 thread_local std::string g_last_error;
 
@@ -461,6 +489,7 @@ gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_ru
   h->ws = (char*)d_workspace;
   h->plan = plan;
   hipError_t e = hipGetDevice(&h->device);
+  if (e == hipSuccess) e = resolve_static_scratch(h->device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipHostMalloc((void**)&h->pinned, sizeof(int32_t) * kStWords * n_runs, hipHostMallocDefault);
   if (e != hipSuccess) {
@@ -1382,6 +1411,17 @@ gsgp_status gsgp_reconstruct(gsgp_handle* h, int32_t run, int32_t gen, int32_t i
   if (st != GSGP_OK) return st;
   if (!d_scratch || ((uintptr_t)d_scratch) % kAlign) return fail(GSGP_ERR_WORKSPACE, "scratch must be non-NULL and 256-byte aligned");
   return reconstruct_with(h, run, gen, individual, d_X, n, d_out, (char*)d_scratch, scratch_bytes, "the scratch");
+}
+
+gsgp_status gsgp_reconstruct_static(gsgp_handle* h, int32_t run, int32_t gen, int32_t individual, const double* d_X,
+                                    int64_t n, double* d_out) {
+  gsgp_status st = check_reconstruct_args(h, run, gen, individual, d_X, n, d_out);
+  if (st != GSGP_OK) return st;
+  if (h->device < 0 || h->device >= kMaxDevices || !g_static[h->device].ptr)
+    return fail(GSGP_ERR_UNSUPPORTED, "no static scratch on device %d", h->device);
+  std::lock_guard<std::mutex> lock(g_static[h->device].call);
+  return reconstruct_with(h, run, gen, individual, d_X, n, d_out, g_static[h->device].ptr, kStaticScratchBytes,
+                          "the static scratch");
 }
 
 

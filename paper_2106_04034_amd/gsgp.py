@@ -36,7 +36,8 @@ STATS_DTYPE = np.dtype([("best_train_rmse", "<f8"), ("best_test_rmse", "<f8"),
 # Every entry point declared in include/gsgp.h.
 EXPORTS = [
     "gsgp_workspace_size", "gsgp_init", "gsgp_eval_population", "gsgp_generation",
-    "gsgp_generation_replay", "gsgp_reconstruct_scratch_size", "gsgp_reconstruct", "gsgp_export_linear",
+    "gsgp_generation_replay", "gsgp_reconstruct_scratch_size", "gsgp_reconstruct", "gsgp_reconstruct_static",
+    "gsgp_export_linear",
     "gsgp_current_generation", "gsgp_get_fitness", "gsgp_get_semantics", "gsgp_get_semantics_rows",
     "gsgp_get_semantics_cases",
     "gsgp_get_records",
@@ -94,6 +95,7 @@ def lib():
             "gsgp_generation_replay": [P, I32, P, P, P],
             "gsgp_reconstruct_scratch_size": [P, I32, I32, I32, I64, P],
             "gsgp_reconstruct": [P, I32, I32, I32, P, I64, P, P, ctypes.c_size_t],
+            "gsgp_reconstruct_static": [P, I32, I32, I32, P, I64, P],
             "gsgp_export_linear": [P, I32, I32, I32, P, P, P],
             "gsgp_current_generation": [P, P],
             "gsgp_get_fitness": [P, I32, P, P],
@@ -369,6 +371,20 @@ class Runner:
             check(lib().gsgp_reconstruct(self._h, run, gen, individual, ctypes.c_void_p(dX.data_ptr()), n,
                                          ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(sp),
                                          int(size.value)), "gsgp_reconstruct")
+            return out.cpu().numpy()
+
+    def reconstruct_static(self, run: int, gen: int, individual: int, X: np.ndarray) -> np.ndarray:
+        """reconstruct() through the entry point that uses the library's own
+        device scratch array (no scratch allocation)."""
+        torch = self.torch
+        X = np.ascontiguousarray(X, np.float64)
+        n = X.shape[0]
+        with torch.cuda.device(self.device):
+            dX = torch.as_tensor(X, device=self.device)
+            out = torch.empty(n, dtype=torch.float64, device=self.device)
+            torch.cuda.synchronize(self.device)
+            check(lib().gsgp_reconstruct_static(self._h, run, gen, individual, ctypes.c_void_p(dX.data_ptr()), n,
+                                                ctypes.c_void_p(out.data_ptr())), "gsgp_reconstruct_static")
             return out.cpu().numpy()
 
     # -- measurement -------------------------------------------------------
