@@ -21,8 +21,8 @@ near ties, whose relative fitness gap is bounded and reported).
     FP64 for every case) follows the lineage on a fixed slice of the cases
     (the first 1/8 of the train and of the test cases): the slice RMSE of
     every individual within 1e-4 relative, and every element of the slice
-    within 1e-4 * max(|oracle|, RMS(t), RMS of the individual's row) (FP32
-    rounding of operands that cancel, see _slice_check);
+    within 1e-4 * max(E, RMS(t)), E the running error scale of FP32 storage
+    along the lineage (see _Envelope);
   - precision_1m (large_fp32_1m data, m = r = 1,024): the FP64 replay of an
     FP32-Kahan lineage, which the precision benchmark uses as its drift
     reference, against the oracle for the first 50 generations on a 1/16
@@ -160,27 +160,71 @@ def _slice(d, frac):
     return ntr, nte, (d.X_train[:ntr], d.y_train[:ntr], d.X_test[:nte], d.y_test[:nte])
 
 
-def _slice_check(R, d, ntr, nte, tol, worst, row_scale=False):
+class _Envelope:
+    """Running error scale of FP32 storage along a lineage (the standard
+    running error bound, Higham, Accuracy and Stability of Numerical
+    Algorithms, ch. 3): every operator evaluated on magnitudes,
+      generation 0:  E = |S|
+      mutation:      E_O = E[p1] + ms * (sR[r1] + sR[r2])
+      crossover:     E_O = E[p1] * sR[r1] + E[p2] * (1 - sR[r1])
+                           + sR[r1] * (E[p1] + E[p2])
+      elite copy:    E_O[dst] = E[src]
+    (sR in (0, 1)).  The crossover's last term is the FP32 rounding of the
+    stored sR itself, which moves the result by (S[p1] - S[p2]) times that
+    rounding: with sR = 1 - 2e-8 stored as exactly 1.0, S[p2] (1 - sR) drops
+    out whatever the size of S[p2].  A value formed in FP32 from
+    FP32-stored operands, g generations deep, differs from the exact one by
+    at most about 6 g u E (u = 2^-24: rounding of each stored operand, of
+    the products and of the sums), however much the operands cancel; the
+    parity bar is then tol * max(E, RMS(t)).  The oracle's own pool
+    semantics on the case slice give sR; the lineage is the device's, as in
+    the replay."""
+
+    def __init__(self, R, sig_tr, sig_te):
+        self.R, self.sig = R, (sig_tr.astype(np.float32), sig_te.astype(np.float32))
+        self.E = None
+
+    def step(self, g, S_tr, S_te):
+        if g == 0:
+            self.E = [np.abs(S_tr).astype(np.float32), np.abs(S_te).astype(np.float32)]
+            return self.E
+        rec = self.R.records(0, g, 1)[0]
+        st = self.R.stats(0, g, 1)[0]
+        xo = rec["op"] == 1
+        ms = rec["ms"].astype(np.float32)[:, None]
+        out = []
+        for E, sig in zip(self.E, self.sig):
+            s1 = sig[rec["r1"]]
+            E1, E2 = E[rec["p1"]], E[np.where(xo, rec["p2"], 0)]
+            O = np.where(xo[:, None], E1 * s1 + E2 * (1 - s1) + s1 * (E1 + E2),
+                         E1 + ms * (s1 + sig[np.where(xo, 0, rec["r2"])]))
+            if st["elite_copied"]:
+                O[st["elite_dst"]] = E[st["elite_src"]]
+            out.append(O)
+        self.E = out
+        return out
+
+
+def _slice_check(R, d, ntr, nte, tol, worst, envelope=None):
     """Compares the device's population on the case slice with the oracle's.
-    Element errors are relative to max(|oracle|, RMS(t)); with row_scale
-    (FP32 storage) also to the RMS of the individual's own row, because a
-    crossover of two large rows that nearly cancel at a case keeps the FP32
-    rounding of its operands (about u times their magnitude), however small
-    the result there."""
+    Element errors are relative to max(|oracle|, RMS(t)), or with an
+    envelope (FP32 storage) to max(E, RMS(t)) with E the running error scale
+    of _Envelope: a crossover of two large rows that nearly cancel at a case
+    keeps the FP32 rounding of its operands, however small the result
+    there."""
     n_train = d.X_train.shape[0]
     floor = float(np.sqrt(np.mean(d.y_train[:ntr] ** 2)))
-
-    def scale(b):
-        f = np.maximum(np.abs(b), floor)
-        if row_scale:
-            f = np.maximum(f, np.sqrt(np.mean(b ** 2, axis=1))[:, None])
-        return f
 
     def check(g, S_tr, S_te, F, Ft):
         A = R.semantics_cases(0, 0, 0, ntr)
         B = R.semantics_cases(0, 0, n_train, nte)
-        worst["sem"] = max(worst["sem"], float(np.max(np.abs(A - S_tr) / scale(S_tr))),
-                           float(np.max(np.abs(B - S_te) / scale(S_te))))
+        if envelope is not None:
+            E_tr, E_te = envelope.step(g, S_tr, S_te)
+            sc_tr, sc_te = np.maximum(E_tr, floor), np.maximum(E_te, floor)
+        else:
+            sc_tr, sc_te = np.maximum(np.abs(S_tr), floor), np.maximum(np.abs(S_te), floor)
+        worst["sem"] = max(worst["sem"], float(np.max(np.abs(A - S_tr) / sc_tr)),
+                           float(np.max(np.abs(B - S_te) / sc_te)))
         f_tr = np.sqrt(np.mean((A - d.y_train[:ntr]) ** 2, axis=1))
         f_te = np.sqrt(np.mean((B - d.y_test[:nte]) ** 2, axis=1))
         worst["fit"] = max(worst["fit"], _rel(f_tr, F, 1e-300), _rel(f_te, Ft, 1e-300))
@@ -200,8 +244,11 @@ def test_large_fp32_1m_drift_on_a_case_slice():
     R.eval_population()
     ntr, nte, data = _slice(d, 8)
     worst = {"sem": 0.0, "fit": 0.0}
-    res = orc.run(oracle_config(s), *data, G, drive=_Lineage(R).pair(),
-                  on_generation=_slice_check(R, d, ntr, nte, 1e-4, worst, row_scale=True))
+    cfg = oracle_config(s)
+    cr, vr = orc.genomes(cfg, wl.n_features, orc.TAG_POOL, s.pool_size)
+    env = _Envelope(R, orc.sigmoid(orc.interpret(cr, vr, data[0])), orc.sigmoid(orc.interpret(cr, vr, data[2])))
+    res = orc.run(cfg, *data, G, drive=_Lineage(R).pair(),
+                  on_generation=_slice_check(R, d, ntr, nte, 1e-4, worst, envelope=env))
     # the oracle's own decisions use the slice's fitness, so its replay check
     # is informative only: the draws themselves must still match
     assert all(c["draw_mismatch"] == 0 for c in res.replay)
