@@ -21,6 +21,11 @@ FLAGS = [
     "-ffp-contract=off",
     # keep the compiler from emitting packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # branch regions whose conditions are wave-uniform keep plain scalar
+    # branches (the interpreter dispatches every op on uniform op bits;
+    # structurizing them as if divergent costs vector compares and exec
+    # masking per op)
+    "-mllvm", "-structurizecfg-skip-uniform-regions=true",
     "-Wall", "-Wno-unused-result",
 ]
 

@@ -54,7 +54,8 @@ constexpr int kOpPad = 8;
 // (kClsFeature / kClsConst) that applies the function to the top of the
 // stack and the terminal, leaving the rest of the stack untouched.  The op's
 // constant slot holds the constant of a constant op and, for a feature op,
-// the bits of the 64-bit row offset feature * ld in the run's X.
+// the bits of the absolute address of the feature's row in the run's X.  The
+// word after a program's last op is an end word (push class, bit 1 set).
 enum OpClass : int32_t { kClsPush = 0, kClsStack = 1, kClsFeature = 2, kClsConst = 3 };
 enum OpFn : int32_t { kFnAdd = 0, kFnSub = 1, kFnMul = 2, kFnDiv = 3 };
 enum OpPush : int32_t { kPushFeature = 0, kPushConst = 1 };
@@ -182,8 +183,8 @@ hipError_t launch_compile(const RunDev* d_runs, const Params& p, hipStream_t s);
 // from every program (deep_max < 0) or from each run's deep list (at most
 // deep_max programs per run).  launch_interpret: two cases per lane, any
 // slots up to kMaxLdsSlots; launch_interpret_wide: four cases per lane,
-// slots kShallowSlots or kWideDeepSlots, for runs whose rows of X are
-// shorter than 4 GiB.
+// slots kShallowSlots or kWideDeepSlots, for runs whose X is smaller than
+// 2 GiB.
 hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_blocks, int lo, int slots,
                             int32_t deep_max, hipStream_t s);
 hipError_t launch_interpret_wide(const RunDev* d_runs, const Params& p, int64_t case_blocks, int lo, int slots,

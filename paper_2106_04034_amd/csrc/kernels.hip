@@ -209,6 +209,10 @@ __global__ __launch_bounds__(256) void k_genome(const RunDev* __restrict__ runs,
   R.cval[local] = val;
 }
 
+// End of a compiled program for eval_program_wide: a push-class word with
+// bit 1 set (a push uses only bit 0).
+constexpr int32_t kOpEnd = 2;
+
 // Compile a genome: drop the functions the stack machine would skip (fewer
 // than two operands) and everything after the last function that runs, and
 // store each op's stack depth so the interpreter needs no depth counter.
@@ -271,6 +275,10 @@ __global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs
     peak = depth > peak ? depth : peak;
   }
   R.nops[prog] = last;
+  // the end word of eval_program_wide: a program with a valid function
+  // starts with a push fused into it, so last <= k - 1 and the word stays in
+  // the program's row (a program without one gets it at 0)
+  ops[last] = kOpEnd;
   const int need = deepest > 2 ? deepest - 2 : 0;  // the top two values live in registers
   R.need[prog] = need;
   if (need > kShallowSlots) R.deep[atomicAdd(&R.state[kStDeepCount], 1)] = prog;
@@ -422,14 +430,19 @@ __device__ __forceinline__ void eval_program(const int32_t* ops, const double* o
 //     function of the top two values, else a push; bit 1 multiplication or
 //     division, bit 0 subtraction or division (or, for a push, a constant).
 //   - A feature op's constant slot holds the absolute address of its row of
-//     the run's X; each lane adds a fixed 32-bit byte offset (its case), so
-//     a feature load needs no address arithmetic at all.
+//     the run's X.  Features are read through a buffer resource over the
+//     run's X (smaller than 2 GiB): the scalar offset is the row's byte
+//     offset (one scalar subtraction) and each lane's fixed 32-bit byte
+//     offset (its case) is the vector offset, so a feature load takes no
+//     vector address arithmetic at all.
 //   - Both function forms share one `apply` (tos = f(tos, b)): a function of
 //     the top two values first moves them into place.
+//   - The program ends at its end word (kOpEnd), tested only on the push
+//     path, instead of a count compared before every op.
 // The FP64 operations and their order are those of eval_program, so results
 // are the same bits.
 template <int V, typename Stack>
-__device__ __forceinline__ void eval_program_wide(const int32_t* ops, const double* opv, int n,
+__device__ __forceinline__ void eval_program_wide(const int32_t* ops, const double* opv, const double* X,
                                                   const uint32_t (&off)[V], Stack stk, int lane, double (&out)[V]) {
   constexpr int kBatch = kOpPad;
   const GSGP_CONST int32_t* cops = (const GSGP_CONST int32_t*)ops;
@@ -440,10 +453,15 @@ __device__ __forceinline__ void eval_program_wide(const int32_t* ops, const doub
     tos[v] = 0.0;
     nos[v] = 0.0;
   }
+  // raw buffer over X: no stride, num_records at the largest offset, and the
+  // third descriptor word of a plain dword buffer on gfx9-family parts
+  const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, 0x7fffffff, 0x00020000);
+  const uint64_t xbase = (uint64_t)X;
   auto feature = [&](double c, double (&x)[V]) {
-    const GSGP_GLOBAL char* row = (const GSGP_GLOBAL char*)__double_as_longlong(c);
+    const int row = (int)((uint64_t)__double_as_longlong(c) - xbase);
 #pragma unroll
-    for (int v = 0; v < V; ++v) x[v] = *(const GSGP_GLOBAL double*)(row + off[v]);
+    for (int v = 0; v < V; ++v)
+      x[v] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(xr, (int)off[v], row, 0));
   };
   auto clamp = [](double x) { return fmin(fmax(x, -kFltMax), kFltMax); };
   auto apply = [&](int w, const double (&b)[V]) {
@@ -469,19 +487,18 @@ __device__ __forceinline__ void eval_program_wide(const int32_t* ops, const doub
       }
     }
   };
-  for (int j0 = 0; j0 < n; j0 += kBatch) {
+  for (int j0 = 0;; j0 += kBatch) {
     int wv[kBatch];
     double cv[kBatch];
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
-      // one batch per two scalar loads; reads past a program's end stay
-      // inside the buffers' padding and are never used
+      // one batch per two scalar loads; reads past a program's end word
+      // stay inside the buffers' padding and are never used
       wv[u] = cops[j0 + u];
       cv[u] = copv[j0 + u];
     }
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
-      if (j0 + u >= n) break;
       const int w = wv[u];
       if (w & 8) {  // fused: tos = f(tos, terminal)
         double b[V];
@@ -506,6 +523,7 @@ __device__ __forceinline__ void eval_program_wide(const int32_t* ops, const doub
           for (int v = 0; v < V; ++v) nos[v] = stk[((d - 3) * V + v) * kWave + lane];
         }
       } else {  // push: nos to LDS, tos to nos, the terminal to tos
+        if (w & 2) goto done;  // kOpEnd
         const int d = (w >> 4) & kOpDepthMax;
         if (d >= 2) {
 #pragma unroll
@@ -522,6 +540,7 @@ __device__ __forceinline__ void eval_program_wide(const int32_t* ops, const doub
       }
     }
   }
+done:
 #pragma unroll
   for (int v = 0; v < V; ++v) out[v] = tos[v];
 }
@@ -617,8 +636,9 @@ __global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ ru
 // lane.  The pass takes the programs with lo < need <= SLOTS, from all
 // programs or (deep_pass) from the run's deep list.  Every lane's byte
 // offset into a feature row (its case, or the last column for lanes past
-// it, whose values are never stored) fits in 32 bits: the runtime uses this
-// kernel only when every run's rows are shorter than 4 GiB.
+// it, whose values are never stored) fits in 32 bits, and so does a feature
+// row's offset in X: the runtime uses this kernel only when every run's X
+// is smaller than 2 GiB.
 constexpr int kWideV = 4;
 constexpr int kWideTile = kWave * kWideV;
 constexpr int kWideWaves = 4;
@@ -655,8 +675,8 @@ __global__ __launch_bounds__(kWideWaves * kWave) void k_interpret_wide(const Run
     off[v] = (uint32_t)((ok[v] ? col[v] : R.ld - 1) * (int64_t)sizeof(double));
   }
   double out[kWideV];
-  eval_program_wide<kWideV>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k, uni(cload(&R.nops[prog])),
-                            off, (LdsStack)(lds + wave * SLOTS * kWideV * kWave), lane, out);
+  eval_program_wide<kWideV>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k, R.X, off,
+                            (LdsStack)(lds + wave * SLOTS * kWideV * kWave), lane, out);
   store_program<T, kWideV>(R, p, prog, col, ok, out);
 }
 

@@ -225,7 +225,7 @@ struct gsgp_handle {
   VaryLaunch vary{}, rows{};
   int64_t interp_tasks = 0;  // interpreter case blocks over all runs
   int64_t interp_tasks_w = 0;  // wide interpreter case blocks over all runs
-  bool interp_wide = false;    // every run's rows of X are shorter than 4 GiB
+  bool interp_wide = false;    // every run's X is smaller than 2 GiB
   int32_t surv_blocks = 0;
   int32_t slots = 1;         // interpreter stack values per lane in LDS
   int32_t max_blocks = 0;
@@ -567,7 +567,7 @@ gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_ru
     itask += (q.ld + kInterpCases - 1) / kInterpCases;
     R.cblk0w = itask_w;
     itask_w += (q.ld + 4 * kWave - 1) / (4 * kWave);
-    wide_ok = wide_ok && (uint64_t)q.ld * sizeof(double) < ((uint64_t)1 << 32);
+    wide_ok = wide_ok && (uint64_t)q.ld * q.l * sizeof(double) < ((uint64_t)1 << 31);
     R.surv_blk0 = sblk;
     // survival blocks per run: each copies about 16 KiB of an elite row
     const int64_t nb = ((int64_t)storage_bytes(cfg->precision) * q.ld + 16383) / 16384;
@@ -638,9 +638,9 @@ namespace {
 // ComputeSemantics of every compiled program, in passes by the stack depth
 // a program needs (h->slots is the deepest): every program that fits a
 // small LDS column, then the deep list in larger columns, then the programs
-// beyond any LDS column (spill stacks).  Runs whose rows of X are shorter
-// than 4 GiB (all practical ones) use the four-cases-per-lane kernel for the
-// first two passes.
+// beyond any LDS column (spill stacks).  Handles whose runs each have an X
+// smaller than 2 GiB (all practical ones) use the four-cases-per-lane kernel
+// for the first two passes.
 hipError_t interpret_all(gsgp_handle* h, int32_t deep_max, hipStream_t s) {
   const Params& p = h->params;
   hipError_t e;
