@@ -54,10 +54,12 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2106_04034_amd", "csrc", "kernels.hip")
 
 
 def kernel_digest() -> str:
-    """Digest of the device code's sources (the kernels and the header of
-    shared constants and layouts they include)."""
+    """Digest of the variation kernel's sources: the translation unit that
+    holds it and the headers of shared constants, layouts and device helpers
+    it includes (the interpreter's own unit is not part of it)."""
     h = hashlib.sha256()
-    for path in (KERNEL_SRC, os.path.join(os.path.dirname(KERNEL_SRC), "common.hpp")):
+    d = os.path.dirname(KERNEL_SRC)
+    for path in (KERNEL_SRC, os.path.join(d, "common.hpp"), os.path.join(d, "device.hpp")):
         h.update(open(path, "rb").read())
     return h.hexdigest()[:16]
 
@@ -70,12 +72,13 @@ def distinct_rows(rec: np.ndarray):
     return parents.size, pool.size
 
 
-def vary_bytes(rec: np.ndarray, n_all: int, s: int, m: int, n_chunks: int) -> int:
+def vary_bytes(rec: np.ndarray, n_all: int, s: int, m: int) -> int:
     """Algorithmic bytes of one variation launch: each offspring row written
-    once, each distinct parent and pool row and the target read once, the
-    chunk partial sums written and the records read."""
+    once, each distinct parent and pool row and the target read once, and
+    the variation records read (the chunk partial sums the kernel also
+    writes are not the method's bytes and are not counted)."""
     u_p, u_r = distinct_rows(rec)
-    return s * n_all * (m + u_p + u_r + 1) + 8 * m * n_chunks + 32 * m
+    return s * n_all * (m + u_p + u_r + 1) + 32 * m
 
 
 FP64_VALU_OPS = 78.6e12 / 2  # FP64 vector operations/s (the vendor FLOP/s counts an FMA as two)
@@ -253,10 +256,8 @@ def bench_single(args, wl, data, seed) -> dict:
     ng = min(args.stage_gens, G)
     stages = R.time_stages(ng)
     rec = R.records(0, 1, ng)
-    chunk = 4096 // s_bytes  # canonical chunk: 4 KiB of a semantic row
     n_tr, n_te = data.X_train.shape[0], data.X_test.shape[0]
-    n_chunks = -(-(-(-n_tr // 64) * 64) // chunk) + -(-(-(-n_te // 64) * 64) // chunk)
-    per_launch = float(np.mean([vary_bytes(rec[g], n_all, s_bytes, m, n_chunks) for g in range(ng)]))
+    per_launch = float(np.mean([vary_bytes(rec[g], n_all, s_bytes, m) for g in range(ng)]))
     u = np.array([distinct_rows(rec[g]) for g in range(ng)])
     achieved = per_launch / (stages["vary_ms"] * 1e-3) / 1e9
     traffic = traffic_from_profile(PMC_SUMMARIES[wl.name]) if wl.name in PMC_SUMMARIES and not args.local_search \
@@ -396,11 +397,6 @@ def bench_precision(args) -> dict:
             "forms": report, "end_of_run_within_1e-4": ok}
 
 
-def _n_chunks(n_tr: int, n_te: int, s_bytes: int) -> int:
-    chunk = 4096 // s_bytes  # canonical chunk: 4 KiB of a semantic row
-    return -(-(-(-n_tr // 64) * 64) // chunk) + -(-(-(-n_te // 64) * 64) // chunk)
-
-
 def cpu_baseline_runs(wl, datasets, G: int, seed: int, pick, g_sample: int, threads: int = 0,
                       local_search: bool = False):
     """The FP64 CPU oracle on a fixed subset of the independent runs (every
@@ -527,8 +523,7 @@ def bench_batched(args) -> dict:
     for j, d in enumerate(datasets):
         n_tr, n_te = d.X_train.shape[0], d.X_test.shape[0]
         rj = B.records(j, 1, ng)
-        alg += float(np.mean([vary_bytes(rj[g], n_tr + n_te, 4, wl.pop_size, _n_chunks(n_tr, n_te, 4))
-                              for g in range(ng)]))
+        alg += float(np.mean([vary_bytes(rj[g], n_tr + n_te, 4, wl.pop_size) for g in range(ng)]))
     eval_stages = B.time_eval()
     codes = np.concatenate([B.genomes(j)[0] for j in range(n_runs)])
     n_cases = np.repeat([d.X_train.shape[0] + d.X_test.shape[0] for d in datasets], wl.pop_size + wl.pool_size)
@@ -660,8 +655,7 @@ def bench_paper_shape(args, wl) -> dict:
     ng = min(G, 20)
     stages = R.time_stages(ng)
     rec = R.records(0, 1, ng)
-    n_chunks = -(-(-(-wl.n_train // 64) * 64) // (4096 // 4))
-    per_launch = float(np.mean([vary_bytes(rec[g], wl.n_train, 4, wl.pop_size, n_chunks) for g in range(ng)]))
+    per_launch = float(np.mean([vary_bytes(rec[g], wl.n_train, 4, wl.pop_size) for g in range(ng)]))
     achieved = per_launch / (stages["vary_ms"] * 1e-3) / 1e9
     codes, _ = R.genomes(0)
     interp = interpreter_rate(codes, wl.n_train, ev["compute_semantics_ms"])

@@ -55,7 +55,7 @@ typedef enum {
  * form; the FP32 forms round semantics once when they are stored.
  *   GSGP_FP64        : FP64 semantics, FP64 arithmetic.
  *   GSGP_FP32        : FP32 semantics and arithmetic, plain FP32 sums of
- *                      squared residuals within each 1,024-case chunk.
+ *                      squared residuals within each 512-case chunk.
  *   GSGP_FP32_KAHAN  : as GSGP_FP32 with compensated (Kahan / two-sum)
  *                      chunk sums.
  * Chunk sums are combined in FP64 in a fixed order in every form. */

@@ -7,15 +7,9 @@
 // interpreter and the fitness, cuBLAS I?AMIN / I?AMAX for survival) is prior
 // art; the mapping here is:
 //   k_genome     one thread per gene, counter-based Philox draws;
-//   k_compile    one thread per genome: drops the functions the interpreter
-//                would skip and the pushes after the last function, fuses
-//                each push with a function that directly consumes it, and
-//                records every op's stack depth;
-//   k_interpret  one wavefront per (program, 128 cases): the compiled
-//                program is wave-uniform (no divergence), lanes own cases,
-//                the top of stack lives in registers and the rest of the
-//                stack in a lane-strided LDS column;
-//   k_vary       the hot loop: every offspring row of one 4 KiB case chunk is
+//   k_compile, k_interpret*  (interp.hip) the genome compiler and the
+//                stack-machine interpreter;
+//   k_vary       the hot loop: every offspring row of one 2 KiB case chunk is
 //                formed from its parent and pool rows with 16-byte loads and
 //                non-temporal 16-byte stores, and the chunk's squared
 //                residual sum is reduced across the wave with xor shuffles;
@@ -27,59 +21,10 @@
 // All kernels are compiled without floating-point contraction so that the
 // per-element arithmetic matches the method's definitions operation by
 // operation.
-#include <float.h>
-#include <math.h>
-
-#include <type_traits>
-
-#include "common.hpp"
+#include "device.hpp"
 
 namespace gsgp {
 namespace {
-
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef double d2 __attribute__((ext_vector_type(2)));
-
-template <typename T>
-struct VecOf;
-template <>
-struct VecOf<float> {
-  typedef f4 type;
-  static constexpr int N = 4;
-};
-template <>
-struct VecOf<double> {
-  typedef d2 type;
-  static constexpr int N = 2;
-};
-
-constexpr double kFltMax = 3.4028234663852886e38;  // largest finite binary32 value
-
-__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// Buffers reach the kernels through RunDev as generic pointers; casting to
-// the global address space lets the compiler emit global (not flat) memory
-// instructions, the constant address space gives scalar loads for data no
-// kernel in flight writes (records, compiled programs, generation counter),
-// and the local address space gives LDS instructions for shared memory.
-#define GSGP_GLOBAL __attribute__((address_space(1)))
-#define GSGP_CONST __attribute__((address_space(4)))
-#define GSGP_LDS __attribute__((address_space(3)))
-
-template <typename VT>
-__device__ __forceinline__ VT gload(const void* p) {
-  return *(const GSGP_GLOBAL VT*)p;
-}
-
-template <typename VT>
-__device__ __forceinline__ void gstore_nt(const VT& v, void* p) {
-  __builtin_nontemporal_store(v, (GSGP_GLOBAL VT*)p);
-}
-
-template <typename X>
-__device__ __forceinline__ X cload(const X* p) {
-  return *(const GSGP_CONST X*)p;
-}
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011): ten rounds of two
@@ -118,23 +63,6 @@ __device__ __forceinline__ double draw_u53(uint32_t a, uint32_t b) {
   const double hi = (double)(a >> 5);
   const double lo = (double)(b >> 6);
   return (hi * 67108864.0 + lo) * (1.0 / 9007199254740992.0);
-}
-
-// ---------------------------------------------------------------------------
-// Run lookup: runs are laid out in launch order; find the last run whose
-// first task is <= t.  Single-run launches skip the search.
-template <typename F>
-__device__ __forceinline__ int find_run(int n_runs, int64_t t, F first_of) {
-  if (n_runs == 1) return 0;
-  int lo = 0, hi = n_runs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (first_of(mid) <= t)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
 }
 
 // ---------------------------------------------------------------------------
@@ -207,514 +135,6 @@ __global__ __launch_bounds__(256) void k_genome(const RunDev* __restrict__ runs,
   }
   R.code[local] = code;
   R.cval[local] = val;
-}
-
-// End of a compiled program for eval_program_wide: a push-class word with
-// bit 1 set (a push uses only bit 0).
-constexpr int32_t kOpEnd = 2;
-
-// Compile a genome: drop the functions the stack machine would skip (fewer
-// than two operands) and everything after the last function that runs, and
-// store each op's stack depth so the interpreter needs no depth counter.
-// One thread per genome; also records the deepest stack per run.
-__global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs, Params p,
-                                                 int32_t total) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= total) return;
-  const int rows = p.m + p.r;
-  const int run = g / rows;
-  const int prog = g - run * rows;
-  const RunDev& R = runs[run];
-  const int32_t* code = R.code + (int64_t)prog * p.k;
-  const double* cval = R.cval + (int64_t)prog * p.k;
-  int32_t* ops = R.ops + (int64_t)prog * p.k;
-  double* opv = R.opv + (int64_t)prog * p.k;
-  // deepest: the deepest stack up to the last valid function; pushes after
-  // it are dropped and never run, so they do not count
-  int depth = 0, n = 0, last = 0, deepest = 0, peak = 0;
-  int32_t prev = 0;  // the last op word written, ops[n - 1]
-  for (int q = 0; q < p.k; ++q) {
-    const int32_t c = code[q];
-    // depths before the last function are at most k - 1 <= kOpDepthMax, and
-    // ops after the last function never run; the cap only keeps the field
-    // inside its bits
-    const int dfield = (depth < kOpDepthMax ? depth : kOpDepthMax) << 4;
-    if (c >= 0) {
-      prev = (kClsPush << 2) | kPushFeature | dfield | (c << 16);
-      ops[n] = prev;
-      // the address of the feature's row in this run's X, bit for bit (see eval_program)
-      opv[n] = __longlong_as_double((long long)(R.X + (int64_t)c * R.ld));
-      ++n;
-      ++depth;
-    } else if (c == -5) {
-      prev = (kClsPush << 2) | kPushConst | dfield;
-      ops[n] = prev;
-      opv[n] = cval[q];
-      ++n;
-      ++depth;
-    } else {
-      if (depth < 2) continue;  // skipped by the interpreter
-      const int fn = -1 - c;
-      if (n > 0 && ((prev >> 2) & 3) == kClsPush) {
-        // push b, then op(a, b) with a the value below it: one op on the top
-        // of the stack; the depth field stays the one before the push, the
-        // feature index and the constant stay where the push put them
-        const int cls = (prev & 3) == kPushConst ? kClsConst : kClsFeature;
-        prev = (prev & ~0xF) | (cls << 2) | fn;
-        ops[n - 1] = prev;
-      } else {
-        prev = (kClsStack << 2) | fn | dfield;
-        ops[n] = prev;
-        opv[n] = 0.0;
-        ++n;
-      }
-      --depth;
-      last = n;
-      deepest = peak;
-    }
-    peak = depth > peak ? depth : peak;
-  }
-  R.nops[prog] = last;
-  // the end word of eval_program_wide: a program with a valid function
-  // starts with a push fused into it, so last <= k - 1 and the word stays in
-  // the program's row (a program without one gets it at 0)
-  ops[last] = kOpEnd;
-  const int need = deepest > 2 ? deepest - 2 : 0;  // the top two values live in registers
-  R.need[prog] = need;
-  if (need > kShallowSlots) R.deep[atomicAdd(&R.state[kStDeepCount], 1)] = prog;
-  atomicMax(&R.state[kStMaxDepth], deepest);
-}
-
-// Evaluate one compiled program on V cases per lane (Section 2.2
-// "Interpreter").  The op stream is wave-uniform and read with scalar loads,
-// eight ops per batch in one load of words and one of constants.  Stack
-// element i of depth d (0 = bottom) lives in
-// registers for the top two (tos = d-1, nos = d-2) and in LDS below them,
-// at stk[(i * V + v) * 64 + lane]; a function of the top two values reads
-// its new second operand from LDS only after it has produced its result, so
-// the LDS latency falls outside the op's dependency chain.  A fused op (a
-// push the next function consumes) applies the function to tos and the
-// terminal and touches neither nos nor LDS.  The value of the program is the
-// output of its last function (the Out register), 0.0 if none runs.
-// X is feature-major in global memory, row stride ld; one case block's
-// features stay in L2 while the block's programs run.
-typedef GSGP_LDS double* LdsStack;        // stack column in LDS
-typedef GSGP_GLOBAL double* GlobalStack;  // stack column in the workspace (spill pass)
-
-template <int V, bool BAKED, typename Stack>
-__device__ __forceinline__ void eval_program(const int32_t* ops, const double* opv, int n, const double* X,
-                                             int64_t ld, const int64_t (&col)[V], const bool (&ok)[V],
-                                             Stack stk, int lane, double (&out)[V]) {
-  constexpr int kBatch = kOpPad;
-  const GSGP_CONST int32_t* cops = (const GSGP_CONST int32_t*)ops;
-  const GSGP_CONST double* copv = (const GSGP_CONST double*)opv;
-  double tos[V], nos[V];
-#pragma unroll
-  for (int v = 0; v < V; ++v) {
-    tos[v] = 0.0;
-    nos[v] = 0.0;
-  }
-  // lanes past the last column read the last column instead (no exec-mask
-  // branches around the loads); their values are never stored
-  int64_t at[V];
-#pragma unroll
-  for (int v = 0; v < V; ++v) at[v] = ok[v] ? col[v] : ld - 1;
-  auto feature = [&](int w, double c, double (&x)[V]) {
-    // BAKED: the compile step stored the address of the feature's row in the
-    // handle's own X in the op's constant slot (a pointer's bits, never used
-    // as a number); other callers pass an X of their own and use the index
-    const GSGP_GLOBAL double* xg =
-        BAKED ? (const GSGP_GLOBAL double*)__double_as_longlong(c)
-              : (const GSGP_GLOBAL double*)X + (int64_t)((uint32_t)w >> 16) * ld;
-#pragma unroll
-    for (int v = 0; v < V; ++v) x[v] = xg[at[v]];
-  };
-  for (int j0 = 0; j0 < n; j0 += kBatch) {
-    int wv[kBatch];
-    double cv[kBatch];
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      // one contiguous batch (two scalar loads); the last batch of a program
-      // may read up to kBatch - 1 words past it, which the buffers' padding
-      // after the last program keeps in bounds, and never uses them
-      wv[u] = cops[j0 + u];
-      cv[u] = copv[j0 + u];
-    }
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      if (j0 + u >= n) break;
-      const int w = wv[u];
-      const int cls = (w >> 2) & 3;
-      const int fn = w & 3;
-      const int d = (w >> 4) & kOpDepthMax;  // stack depth before the op
-      if (cls == kClsPush) {
-        if (d >= 2) {
-#pragma unroll
-          for (int v = 0; v < V; ++v) stk[((d - 2) * V + v) * kWave + lane] = nos[v];
-        }
-#pragma unroll
-        for (int v = 0; v < V; ++v) nos[v] = tos[v];
-        if (fn == kPushFeature) {
-          feature(w, cv[u], tos);
-        } else {
-#pragma unroll
-          for (int v = 0; v < V; ++v) tos[v] = cv[u];
-        }
-      } else {
-        // op(a, b): b is the top of the stack (or the fused terminal), a the
-        // value below it (or the top of the stack).  The two forms are
-        // separate call sites of `apply`, so neither first copies its
-        // operands into a common pair of registers.
-        // Every operand is finite (finite features and constants, results
-        // clamped here, protected division), so min/max clamp exactly as a
-        // compare-and-select would.  The clamp sits in each branch, on the
-        // arithmetic result itself, where the compiler knows the value needs
-        // no NaN canonicalisation before min/max.
-        auto clamp = [](double x) { return fmin(fmax(x, -kFltMax), kFltMax); };
-        auto apply = [&](const double (&a)[V], const double (&b)[V]) {
-          if (fn == kFnAdd) {
-#pragma unroll
-            for (int v = 0; v < V; ++v) tos[v] = clamp(a[v] + b[v]);
-          } else if (fn == kFnSub) {
-#pragma unroll
-            for (int v = 0; v < V; ++v) tos[v] = clamp(a[v] - b[v]);
-          } else if (fn == kFnMul) {
-#pragma unroll
-            for (int v = 0; v < V; ++v) tos[v] = clamp(a[v] * b[v]);
-          } else {
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-              // protected division without a per-lane branch: the quotient
-              // of a safe denominator is kept only where |b| >= 1e-6, and
-              // there it is a / b
-              const bool tiny = fabs(b[v]) < 1e-6;
-              const double q = a[v] / (tiny ? 1.0 : b[v]);
-              tos[v] = clamp(tiny ? 1.0 : q);
-            }
-          }
-        };
-        if (cls == kClsStack) {
-          double t0[V];
-#pragma unroll
-          for (int v = 0; v < V; ++v) t0[v] = tos[v];
-          apply(nos, t0);
-        } else {
-          double x[V], t0[V];
-#pragma unroll
-          for (int v = 0; v < V; ++v) t0[v] = tos[v];
-          if (cls == kClsFeature) {
-            feature(w, cv[u], x);
-          } else {
-#pragma unroll
-            for (int v = 0; v < V; ++v) x[v] = cv[u];
-          }
-          apply(t0, x);
-        }
-        if (cls == kClsStack && d >= 3) {
-#pragma unroll
-          for (int v = 0; v < V; ++v) nos[v] = stk[((d - 3) * V + v) * kWave + lane];
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int v = 0; v < V; ++v) out[v] = tos[v];
-}
-
-// The first interpreter passes: eval_program for V cases per lane with the
-// stack's LDS column bounded at compile time, written to keep the scalar
-// work per op small (the kernel is bound by the scalar unit's issue rate:
-// every op is decoded and dispatched by wave-uniform branches).
-//   - Dispatch tests single bits of the op word: bit 3 a function applied
-//     to the top of the stack and a terminal (fused op), else bit 2 a
-//     function of the top two values, else a push; bit 1 multiplication or
-//     division, bit 0 subtraction or division (or, for a push, a constant).
-//   - A feature op's constant slot holds the absolute address of its row of
-//     the run's X.  Features are read through a buffer resource over the
-//     run's X (smaller than 2 GiB): the scalar offset is the row's byte
-//     offset (one scalar subtraction) and each lane's fixed 32-bit byte
-//     offset (its case) is the vector offset, so a feature load takes no
-//     vector address arithmetic at all.
-//   - Both function forms share one `apply` (tos = f(tos, b)): a function of
-//     the top two values first moves them into place.
-//   - The program ends at its end word (kOpEnd), tested only on the push
-//     path, instead of a count compared before every op.
-// The FP64 operations and their order are those of eval_program, so results
-// are the same bits.
-template <int V, typename Stack>
-__device__ __forceinline__ void eval_program_wide(const int32_t* ops, const double* opv, const double* X,
-                                                  const uint32_t (&off)[V], Stack stk, int lane, double (&out)[V]) {
-  constexpr int kBatch = kOpPad;
-  const GSGP_CONST int32_t* cops = (const GSGP_CONST int32_t*)ops;
-  const GSGP_CONST double* copv = (const GSGP_CONST double*)opv;
-  double tos[V], nos[V];
-#pragma unroll
-  for (int v = 0; v < V; ++v) {
-    tos[v] = 0.0;
-    nos[v] = 0.0;
-  }
-  // raw buffer over X: no stride, num_records at the largest offset, and the
-  // third descriptor word of a plain dword buffer on gfx9-family parts
-  const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, 0x7fffffff, 0x00020000);
-  const uint64_t xbase = (uint64_t)X;
-  auto feature = [&](double c, double (&x)[V]) {
-    const int row = (int)((uint64_t)__double_as_longlong(c) - xbase);
-#pragma unroll
-    for (int v = 0; v < V; ++v)
-      x[v] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(xr, (int)off[v], row, 0));
-  };
-  auto clamp = [](double x) { return fmin(fmax(x, -kFltMax), kFltMax); };
-  auto apply = [&](int w, const double (&b)[V]) {
-    if (w & 2) {
-      if (w & 1) {
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-          const bool tiny = fabs(b[v]) < 1e-6;  // protected division, as in eval_program
-          const double q = tos[v] / (tiny ? 1.0 : b[v]);
-          tos[v] = clamp(tiny ? 1.0 : q);
-        }
-      } else {
-#pragma unroll
-        for (int v = 0; v < V; ++v) tos[v] = clamp(tos[v] * b[v]);
-      }
-    } else {
-      if (w & 1) {
-#pragma unroll
-        for (int v = 0; v < V; ++v) tos[v] = clamp(tos[v] - b[v]);
-      } else {
-#pragma unroll
-        for (int v = 0; v < V; ++v) tos[v] = clamp(tos[v] + b[v]);
-      }
-    }
-  };
-  for (int j0 = 0;; j0 += kBatch) {
-    int wv[kBatch];
-    double cv[kBatch];
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      // one batch per two scalar loads; reads past a program's end word
-      // stay inside the buffers' padding and are never used
-      wv[u] = cops[j0 + u];
-      cv[u] = copv[j0 + u];
-    }
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const int w = wv[u];
-      if (w & 8) {  // fused: tos = f(tos, terminal)
-        double b[V];
-        if (w & 4) {
-#pragma unroll
-          for (int v = 0; v < V; ++v) b[v] = cv[u];
-        } else {
-          feature(cv[u], b);
-        }
-        apply(w, b);
-      } else if (w & 4) {  // tos = f(nos, tos), then the new nos from LDS
-        double b[V];
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-          b[v] = tos[v];
-          tos[v] = nos[v];
-        }
-        apply(w, b);
-        const int d = (w >> 4) & kOpDepthMax;
-        if (d >= 3) {
-#pragma unroll
-          for (int v = 0; v < V; ++v) nos[v] = stk[((d - 3) * V + v) * kWave + lane];
-        }
-      } else {  // push: nos to LDS, tos to nos, the terminal to tos
-        if (w & 2) goto done;  // kOpEnd
-        const int d = (w >> 4) & kOpDepthMax;
-        if (d >= 2) {
-#pragma unroll
-          for (int v = 0; v < V; ++v) stk[((d - 2) * V + v) * kWave + lane] = nos[v];
-        }
-#pragma unroll
-        for (int v = 0; v < V; ++v) nos[v] = tos[v];
-        if (w & 1) {
-#pragma unroll
-          for (int v = 0; v < V; ++v) tos[v] = cv[u];
-        } else {
-          feature(cv[u], tos);
-        }
-      }
-    }
-  }
-done:
-#pragma unroll
-  for (int v = 0; v < V; ++v) out[v] = tos[v];
-}
-
-constexpr int kInterpV = 2;              // cases per lane
-constexpr int kInterpTile = kWave * kInterpV;  // cases per block
-static_assert(kInterpTile == kInterpCases, "the runtime plans kInterpCases-case blocks");
-// Programs each wave interprets on its case block.  One per wave keeps the
-// last waves of a launch from holding up its end when programs are long
-// (k = 2,047 at the Section 3.1 shape: 425 ms with one per wave, 449 with
-// four, 468 with eight; k = 127: 29.8 / 30.4 / 31.1 ms) and costs about 1 %
-// on 2,048 programs x 125,000 cases (4.1 against 4.0 ms).  Taking the
-// count as a launch argument instead of a constant cost 3 %.
-constexpr int kInterpProgsPerWave = 1;
-
-// Writes one program's values for one case block: population rows as they
-// are, pool rows squashed by the logistic function (the random functions R_u
-// of GSM, Section 2); padding columns as exact zeros.
-template <typename T, int V>
-__device__ __forceinline__ void store_program(const RunDev& R, const Params& p, int prog, const int64_t (&col)[V],
-                                              const bool (&ok)[V], const double (&out)[V]) {
-  const bool pool = prog >= p.m;
-  T* dst = pool ? (T*)R.sigR : (T*)R.S[0];
-  const int64_t nrows = pool ? p.r : p.m;
-  const int64_t row = pool ? prog - p.m : prog;
-#pragma unroll
-  for (int v = 0; v < V; ++v) {
-    if (!ok[v]) continue;
-    const int64_t c = col[v];
-    const bool real = c < R.n_train || (c >= R.tr_pad && c < R.tr_pad + R.n_test);
-    double val = out[v];
-    if (pool) val = 1.0 / (1.0 + exp(-val));
-    dst[tiled_index(R.tr_pad, R.te_pad, R.nch_tr, chunk_cases(sizeof(T)), nrows, row, c)] = real ? (T)val : (T)0;
-  }
-}
-
-// ComputeSemantics(P) and ComputeSemantics(R) (Algorithm 1).  A block takes
-// one block of 128 cases of one run and a group of programs; each wave
-// interprets kInterpProgsPerWave programs on the block's cases.  The LDS
-// stack column of a wave bounds how many waves a CU holds, and the kernel
-// is latency-bound, so it runs in two passes: every program whose stack
-// fits in kShallowSlots LDS values, then (deep_pass) the run's list of
-// deeper programs with a column sized for the deepest.  Pool rows
-// are squashed by the logistic function (the random functions R_u of GSM,
-// Section 2) before storage.  Padding columns are written as exact zeros.
-// (Staging the case block's features in LDS was slower: the tile cut the
-// number of resident waves more than it saved in L2 reads.)
-template <typename T>
-__global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ runs, Params p, int32_t pgroups,
-                                                   int lo, int slots, int deep_pass) {
-  extern __shared__ double lds[];
-  const int lane = threadIdx.x & 63;
-  const int wave = uni(threadIdx.x >> 6);
-  const int W = blockDim.x >> 6;
-  const int64_t cbg = blockIdx.x / pgroups;  // case block over all runs
-  const int pg = (int)(blockIdx.x - cbg * pgroups);
-  const int run = find_run(p.n_runs, cbg, [&](int r) { return runs[r].cblk0; });
-  const RunDev& R = runs[run];
-  const int64_t cb = cbg - R.cblk0;
-  const int64_t ld = R.ld;
-  const int rows = p.m + p.r;
-  double* stk = lds + wave * slots * kInterpV * kWave;
-  int64_t col[kInterpV];
-  bool ok[kInterpV];
-#pragma unroll
-  for (int v = 0; v < kInterpV; ++v) {
-    col[v] = cb * kInterpTile + v * kWave + lane;
-    ok[v] = col[v] < ld;
-  }
-  for (int j = 0; j < kInterpProgsPerWave; ++j) {
-    const int idx = (pg * kInterpProgsPerWave + j) * W + wave;
-    int prog;
-    if (deep_pass) {
-      if (idx >= uni(cload(&R.state[kStDeepCount]))) break;
-      prog = uni(cload(&R.deep[idx]));
-    } else {
-      if (idx >= rows) break;
-      prog = idx;
-    }
-    // this pass takes the programs with lo < need <= slots
-    const int need = uni(cload(&R.need[prog]));
-    if (need <= lo || need > slots) continue;
-    double out[kInterpV];
-    eval_program<kInterpV, true>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k, uni(cload(&R.nops[prog])),
-                                 R.X, ld, col, ok, (LdsStack)stk, lane, out);
-    store_program<T, kInterpV>(R, p, prog, col, ok, out);
-  }
-}
-
-// ComputeSemantics with eval_program_wide: a block of 4 waves takes one
-// block of kWideTile cases of one run (lanes own kWideV cases each) and
-// 4 programs, one per wave; a wave's LDS column holds SLOTS stack values per
-// lane.  The pass takes the programs with lo < need <= SLOTS, from all
-// programs or (deep_pass) from the run's deep list.  Every lane's byte
-// offset into a feature row (its case, or the last column for lanes past
-// it, whose values are never stored) fits in 32 bits, and so does a feature
-// row's offset in X: the runtime uses this kernel only when every run's X
-// is smaller than 2 GiB.
-constexpr int kWideV = 4;
-constexpr int kWideTile = kWave * kWideV;
-constexpr int kWideWaves = 4;
-
-template <typename T, int SLOTS>
-__global__ __launch_bounds__(kWideWaves * kWave) void k_interpret_wide(const RunDev* __restrict__ runs, Params p,
-                                                                        int32_t pgroups, int lo, int deep_pass) {
-  __shared__ double lds[kWideWaves * SLOTS * kWideV * kWave];
-  const int lane = threadIdx.x & 63;
-  const int wave = uni(threadIdx.x >> 6);
-  const int64_t cbg = blockIdx.x / pgroups;  // case block over all runs
-  const int pg = (int)(blockIdx.x - cbg * pgroups);
-  const int run = find_run(p.n_runs, cbg, [&](int r) { return runs[r].cblk0w; });
-  const RunDev& R = runs[run];
-  const int64_t cb = cbg - R.cblk0w;
-  const int idx = pg * kWideWaves + wave;
-  int prog;
-  if (deep_pass) {
-    if (idx >= uni(cload(&R.state[kStDeepCount]))) return;
-    prog = uni(cload(&R.deep[idx]));
-  } else {
-    if (idx >= p.m + p.r) return;
-    prog = idx;
-  }
-  const int need = uni(cload(&R.need[prog]));
-  if (need <= lo || need > SLOTS) return;
-  int64_t col[kWideV];
-  bool ok[kWideV];
-  uint32_t off[kWideV];
-#pragma unroll
-  for (int v = 0; v < kWideV; ++v) {
-    col[v] = cb * kWideTile + v * kWave + lane;
-    ok[v] = col[v] < R.ld;
-    off[v] = (uint32_t)((ok[v] ? col[v] : R.ld - 1) * (int64_t)sizeof(double));
-  }
-  double out[kWideV];
-  eval_program_wide<kWideV>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k, R.X, off,
-                            (LdsStack)(lds + wave * SLOTS * kWideV * kWave), lane, out);
-  store_program<T, kWideV>(R, p, prog, col, ok, out);
-}
-
-// Third pass: the deep-list programs whose stack exceeds the largest LDS
-// column (need > kMaxLdsSlots).  kSpillWaves waves, one per block, each own
-// a column of `slots` x kInterpV x 64 doubles in `spill` (lane-strided as in
-// LDS, so every stack access is one coalesced 512-byte row) and sweep the
-// (program, case block) tasks of every run in turn.
-template <typename T>
-__global__ __launch_bounds__(64) void k_interpret_spill(const RunDev* __restrict__ runs, Params p, double* spill,
-                                                        int slots) {
-  const int lane = threadIdx.x & 63;
-  const int w = blockIdx.x;
-  double* stk = spill + (int64_t)w * slots * kInterpV * kWave;
-  for (int run = 0; run < p.n_runs; ++run) {
-    const RunDev& R = runs[run];
-    const int cnt = uni(cload(&R.state[kStDeepCount]));
-    const int64_t cblocks = (R.ld + kInterpTile - 1) / kInterpTile;
-    const int64_t tasks = (int64_t)cnt * cblocks;
-    for (int64_t t = w; t < tasks; t += gridDim.x) {
-      const int j = (int)(t / cblocks);
-      const int64_t cb = t - (int64_t)j * cblocks;
-      const int prog = uni(cload(&R.deep[j]));
-      const int need = uni(cload(&R.need[prog]));
-      if (need <= kMaxLdsSlots || need > slots) continue;  // LDS passes took it; never beyond the column
-      int64_t col[kInterpV];
-      bool ok[kInterpV];
-#pragma unroll
-      for (int v = 0; v < kInterpV; ++v) {
-        col[v] = cb * kInterpTile + v * kWave + lane;
-        ok[v] = col[v] < R.ld;
-      }
-      double out[kInterpV];
-      eval_program<kInterpV, true>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k,
-                                   uni(cload(&R.nops[prog])), R.X, R.ld, col, ok, (GlobalStack)stk, lane, out);
-      store_program<T, kInterpV>(R, p, prog, col, ok, out);
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1055,7 +475,7 @@ __device__ __forceinline__ void vary_task(const RunDev& R, const Params& p, cons
 
 // ---------------------------------------------------------------------------
 // GSM / GSC + fitness partials (Algorithm 1 loop: GSM, ComputeFitness).
-// Task = (run, 4 KiB chunk of cases, group of `opb` offspring).  Each wave
+// Task = (run, 2 KiB chunk of cases, group of `opb` offspring).  Each wave
 // takes offspring grp*opb + wave, + waves, ...; per offspring it reads its
 // variation record, forms the chunk of the offspring row
 //   mutation:  O = S[p1] + ms * (sR[r1] - sR[r2])
@@ -1560,71 +980,6 @@ __global__ __launch_bounds__(256) void k_transpose(const double* __restrict__ X,
   for (int f = 0; f < l; ++f) Xfm[(int64_t)f * ld + c] = c < n ? X[c * l + f] : 0.0;
 }
 
-// One (program, 128-case block) task of the list interpreter: nprog
-// programs (prog[j], squashed by the logistic when squash[j]) on cases of
-// the feature-major Xfm, out[j][ld].
-template <typename Stack>
-__device__ __forceinline__ void list_task(const int32_t* ops, const double* opv, const int32_t* nops, int32_t k,
-                                          const int32_t* prog, const int32_t* squash, int32_t nprog,
-                                          const double* Xfm, int64_t ld, int64_t n, double* out, int64_t task,
-                                          Stack stk, int lane) {
-  const int64_t cb = task / nprog;
-  const int j = (int)(task - cb * nprog);
-  const int pr = uni(prog[j]);
-  int64_t col[kInterpV];
-  bool ok[kInterpV];
-#pragma unroll
-  for (int v = 0; v < kInterpV; ++v) {
-    col[v] = cb * (kWave * kInterpV) + v * kWave + lane;
-    ok[v] = col[v] < ld;
-  }
-  double val[kInterpV];
-  eval_program<kInterpV, false>(ops + (int64_t)pr * k, opv + (int64_t)pr * k, uni(nops[pr]), Xfm, ld, col, ok, stk,
-                                lane, val);
-  const bool sq = squash[j] != 0;
-#pragma unroll
-  for (int v = 0; v < kInterpV; ++v) {
-    if (!ok[v]) continue;
-    double x = val[v];
-    if (sq) x = 1.0 / (1.0 + exp(-x));
-    out[(int64_t)j * ld + col[v]] = col[v] < n ? x : 0.0;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_interpret_list(const int32_t* __restrict__ ops,
-                                                        const double* __restrict__ opv,
-                                                        const int32_t* __restrict__ nops, int32_t k,
-                                                        const int32_t* __restrict__ prog,
-                                                        const int32_t* __restrict__ squash,
-                                                        int32_t nprog, const double* __restrict__ Xfm,
-                                                        int64_t ld, int64_t n, double* __restrict__ out,
-                                                        int slots, int64_t total) {
-  extern __shared__ double lds[];
-  const int lane = threadIdx.x & 63;
-  const int wave = uni(threadIdx.x >> 6);
-  const int64_t task = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
-  if (task >= total) return;
-  double* stk = lds + wave * slots * kInterpV * kWave;
-  list_task(ops, opv, nops, k, prog, squash, nprog, Xfm, ld, n, out, task, (LdsStack)stk, lane);
-}
-
-// The same with stacks deeper than an LDS column: kSpillWaves one-wave
-// blocks, each with a column of `slots` x kInterpV x 64 doubles in `spill`,
-// sweep the tasks.
-__global__ __launch_bounds__(64) void k_interpret_list_spill(const int32_t* __restrict__ ops,
-                                                             const double* __restrict__ opv,
-                                                             const int32_t* __restrict__ nops, int32_t k,
-                                                             const int32_t* __restrict__ prog,
-                                                             const int32_t* __restrict__ squash,
-                                                             int32_t nprog, const double* __restrict__ Xfm,
-                                                             int64_t ld, int64_t n, double* __restrict__ out,
-                                                             double* spill, int slots, int64_t total) {
-  const int lane = threadIdx.x & 63;
-  double* stk = spill + (int64_t)blockIdx.x * slots * kInterpV * kWave;
-  for (int64_t task = blockIdx.x; task < total; task += gridDim.x)
-    list_task(ops, opv, nops, k, prog, squash, nprog, Xfm, ld, n, out, task, (GlobalStack)stk, lane);
-}
-
 __global__ __launch_bounds__(256) void k_replay_nodes(const ReplayNode* __restrict__ nodes,
                                                       const double* __restrict__ prev,
                                                       const double* __restrict__ pool,
@@ -1654,15 +1009,7 @@ __global__ void k_set_state(const RunDev* __restrict__ runs, int32_t n_runs, int
   if (r < n_runs) runs[r].state[word] = value;
 }
 
-inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
-// Waves per interpreter block so that the LDS stacks of one block stay
-// within 64 KiB: each wave needs slots * kInterpV * 64 doubles.
-inline int interp_waves(int slots) {
-  const int per_wave = slots * kInterpV * kWave * (int)sizeof(double);
-  int w = 65536 / per_wave;
-  return w < 1 ? 1 : (w > 4 ? 4 : w);
-}
 
 }  // namespace
 
@@ -1690,74 +1037,6 @@ hipError_t launch_prep(const RunDev* d_runs, const Params& p, int64_t total_cols
 hipError_t launch_genome(const RunDev* d_runs, const Params& p, hipStream_t s) {
   const int64_t total = (int64_t)p.n_runs * (p.m + p.r) * p.k;
   hipLaunchKernelGGL(k_genome, dim3(blocks_for(total, 256)), dim3(256), 0, s, d_runs, p, total);
-  return hipGetLastError();
-}
-
-hipError_t launch_compile(const RunDev* d_runs, const Params& p, hipStream_t s) {
-  const int32_t total = p.n_runs * (p.m + p.r);
-  hipLaunchKernelGGL(k_compile, dim3(blocks_for(total, 256)), dim3(256), 0, s, d_runs, p, total);
-  return hipGetLastError();
-}
-
-hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_blocks, int lo, int slots,
-                            int32_t deep_max, hipStream_t s) {
-  if (slots < 1) slots = 1;
-  if (slots > kMaxLdsSlots) return hipErrorInvalidValue;  // deeper stacks take the spill pass
-  if (deep_max == 0) return hipSuccess;
-  // one LDS stack column block per wave, at most 64 KiB per block
-  const int waves = interp_waves(slots);
-  const size_t shmem = (size_t)waves * slots * kInterpV * kWave * sizeof(double);
-  const int progs = deep_max > 0 ? deep_max : p.m + p.r;
-  const int32_t pgroups = (progs + waves * kInterpProgsPerWave - 1) / (waves * kInterpProgsPerWave);
-  // any workspace that fits on the device keeps this far below the limit
-  if (case_blocks * pgroups > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  const dim3 grid((unsigned)(case_blocks * pgroups)), block(waves * kWave);
-  const int deep_pass = deep_max > 0 ? 1 : 0;
-  if (p.precision == GSGP_FP64)
-    hipLaunchKernelGGL((k_interpret<double>), grid, block, shmem, s, d_runs, p, pgroups, lo, slots, deep_pass);
-  else
-    hipLaunchKernelGGL((k_interpret<float>), grid, block, shmem, s, d_runs, p, pgroups, lo, slots, deep_pass);
-  return hipGetLastError();
-}
-
-template <typename T, int SLOTS>
-void launch_wide_as(const RunDev* d_runs, const Params& p, dim3 grid, int32_t pgroups, int lo, int deep_pass,
-                    hipStream_t s) {
-  hipLaunchKernelGGL((k_interpret_wide<T, SLOTS>), grid, dim3(kWideWaves * kWave), 0, s, d_runs, p, pgroups, lo,
-                     deep_pass);
-}
-
-hipError_t launch_interpret_wide(const RunDev* d_runs, const Params& p, int64_t case_blocks, int lo, int slots,
-                                 int32_t deep_max, hipStream_t s) {
-  if (deep_max == 0) return hipSuccess;
-  if (slots != kShallowSlots && slots != kWideDeepSlots) return hipErrorInvalidValue;
-  const int progs = deep_max > 0 ? deep_max : p.m + p.r;
-  const int32_t pgroups = (progs + kWideWaves - 1) / kWideWaves;
-  if (case_blocks * pgroups > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  const dim3 grid((unsigned)(case_blocks * pgroups));
-  const int deep_pass = deep_max > 0 ? 1 : 0;
-  if (p.precision == GSGP_FP64) {
-    if (slots == kShallowSlots)
-      launch_wide_as<double, kShallowSlots>(d_runs, p, grid, pgroups, lo, deep_pass, s);
-    else
-      launch_wide_as<double, kWideDeepSlots>(d_runs, p, grid, pgroups, lo, deep_pass, s);
-  } else {
-    if (slots == kShallowSlots)
-      launch_wide_as<float, kShallowSlots>(d_runs, p, grid, pgroups, lo, deep_pass, s);
-    else
-      launch_wide_as<float, kWideDeepSlots>(d_runs, p, grid, pgroups, lo, deep_pass, s);
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_interpret_spill(const RunDev* d_runs, const Params& p, double* spill, int slots,
-                                  hipStream_t s) {
-  if (slots <= kMaxLdsSlots) return hipSuccess;
-  if (!spill) return hipErrorInvalidValue;
-  if (p.precision == GSGP_FP64)
-    hipLaunchKernelGGL((k_interpret_spill<double>), dim3(kSpillWaves), dim3(kWave), 0, s, d_runs, p, spill, slots);
-  else
-    hipLaunchKernelGGL((k_interpret_spill<float>), dim3(kSpillWaves), dim3(kWave), 0, s, d_runs, p, spill, slots);
   return hipGetLastError();
 }
 
@@ -1851,27 +1130,6 @@ hipError_t launch_survive(const RunDev* d_runs, const Params& p, int32_t total_b
 hipError_t launch_transpose(const double* X, int64_t n, int32_t l, double* Xfm, int64_t ld,
                             hipStream_t s) {
   hipLaunchKernelGGL(k_transpose, dim3(blocks_for(ld, 256)), dim3(256), 0, s, X, n, l, Xfm, ld);
-  return hipGetLastError();
-}
-
-hipError_t launch_interpret_list(const int32_t* ops, const double* opv, const int32_t* nops,
-                                 int32_t k, const int32_t* prog, const int32_t* squash,
-                                 int32_t nprog, const double* Xfm, int64_t ld, int64_t n,
-                                 double* out, int slots, double* spill, hipStream_t s) {
-  if (nprog <= 0) return hipSuccess;
-  if (slots < 1) slots = 1;
-  const int64_t cblocks = (ld + kWave * kInterpV - 1) / (kWave * kInterpV);
-  const int64_t total = cblocks * nprog;
-  if (slots > kMaxLdsSlots) {
-    if (!spill) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_interpret_list_spill, dim3(kSpillWaves), dim3(kWave), 0, s, ops, opv, nops, k, prog,
-                       squash, nprog, Xfm, ld, n, out, spill, slots, total);
-    return hipGetLastError();
-  }
-  const int waves = interp_waves(slots);
-  const size_t shmem = (size_t)waves * slots * kInterpV * kWave * sizeof(double);
-  hipLaunchKernelGGL(k_interpret_list, dim3(blocks_for(total, waves)), dim3(waves * kWave),
-                     shmem, s, ops, opv, nops, k, prog, squash, nprog, Xfm, ld, n, out, slots, total);
   return hipGetLastError();
 }
 

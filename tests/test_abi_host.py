@@ -160,7 +160,8 @@ def test_host_code_under_address_sanitizer(tmp_path):
     subprocess.check_call([hipcc, "--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC", "-shared",
                            "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                            *host_only, "-o", lib, os.path.join(csrc, "kernels.hip"),
-                           os.path.join(csrc, "runtime.hip")], stderr=subprocess.DEVNULL)
+                           os.path.join(csrc, "interp.hip"), os.path.join(csrc, "runtime.hip")],
+                          stderr=subprocess.DEVNULL)
     env = dict(os.environ, LD_PRELOAD=rt, GSGP_LIBRARY=lib,
                ASAN_OPTIONS="detect_leaks=0:alloc_dealloc_mismatch=0:detect_odr_violation=0")
     out = subprocess.run([sys.executable, "-m", "pytest", "-q", "-p", "no:cacheprovider",

@@ -40,7 +40,7 @@ def _records(rng, m, r, p_xo):
 @pytest.mark.parametrize("p_xo", [0.0, 0.5, 1.0])
 def test_variation_bytes_count_each_distinct_row_once(p_xo):
     rng = np.random.default_rng(3)
-    m, r, n_all, s, n_chunks = 200, 150, 1000, 4, 3
+    m, r, n_all, s = 200, 150, 1000, 4
     rec = _records(rng, m, r, p_xo)
     parents, pool = set(), set()
     for x in rec:
@@ -52,8 +52,8 @@ def test_variation_bytes_count_each_distinct_row_once(p_xo):
             pool.add(int(x["r1"]))
             pool.add(int(x["r2"]))
     assert bench.distinct_rows(rec) == (len(parents), len(pool))
-    want = s * n_all * (m + len(parents) + len(pool) + 1) + 8 * m * n_chunks + 32 * m
-    assert bench.vary_bytes(rec, n_all, s, m, n_chunks) == want
+    want = s * n_all * (m + len(parents) + len(pool) + 1) + 32 * m
+    assert bench.vary_bytes(rec, n_all, s, m) == want
 
 
 def _steps_one(genome):
@@ -104,11 +104,12 @@ def test_interpreter_rate_weights_each_genome_by_its_run_cases():
     assert bench.interpreter_rate(codes, 50, 1.0)["gene_steps"] == bench.gene_steps(codes) * 50
 
 
-def test_kernel_digest_covers_the_kernels_and_their_shared_header(tmp_path, monkeypatch):
-    for name in ("kernels.hip", "common.hpp"):
+def test_kernel_digest_covers_the_kernels_and_their_shared_headers(tmp_path, monkeypatch):
+    for name in ("kernels.hip", "common.hpp", "device.hpp"):
         (tmp_path / name).write_bytes(open(os.path.join(os.path.dirname(bench.KERNEL_SRC), name), "rb").read())
     monkeypatch.setattr(bench, "KERNEL_SRC", str(tmp_path / "kernels.hip"))
-    d0 = bench.kernel_digest()
-    with open(tmp_path / "common.hpp", "ab") as f:
-        f.write(b"\n")
-    assert bench.kernel_digest() != d0
+    for name in ("common.hpp", "device.hpp"):
+        d0 = bench.kernel_digest()
+        with open(tmp_path / name, "ab") as f:
+            f.write(b"\n")
+        assert bench.kernel_digest() != d0, name
