@@ -38,12 +38,22 @@ constexpr int kSpillWaves = 128;
 // Stack values below the top two that a genome of k genes can need: its
 // deepest stack up to its last valid function is at most k - 1 values.
 constexpr int64_t max_need(int64_t k) { return k > 3 ? k - 3 : 0; }
-// Programs whose stack needs more than this many LDS values per lane form a
-// run's deep list (the later interpreter passes read it); the first pass
-// takes every program within it with a small LDS column per wave.
-constexpr int kShallowSlots = 2;
-// LDS column of the second (wide) pass over the deep list.
-constexpr int kWideDeepSlots = 6;
+// The interpreter runs in passes by stack need (LDS values per lane below
+// the two stack values kept in registers), each with the smallest LDS
+// column that holds its programs, so that a CU keeps as many waves resident
+// as the column allows: the compile step files each run's programs into
+// kLists lists; list b < kLists - 1 holds the programs whose need lies in
+// (kListSlots[b - 1], kListSlots[b]] (list 0: need <= kListSlots[0]); the
+// last list holds every deeper program (two-cases-per-lane passes with
+// columns up to kMaxLdsSlots, then the spill pass).
+constexpr int kLists = 5;
+constexpr int kListSlots[kLists - 1] = {2, 3, 4, 6};
+__host__ __device__ constexpr int list_of(int need) {
+  return need <= 2 ? 0 : need == 3 ? 1 : need == 4 ? 2 : need <= 6 ? 3 : 4;
+}
+static_assert(list_of(kListSlots[0]) == 0 && list_of(kListSlots[1]) == 1 && list_of(kListSlots[2]) == 2 &&
+                  list_of(kListSlots[3]) == 3 && list_of(kListSlots[3] + 1) == kLists - 1,
+              "list_of must follow kListSlots");
 // The interpreter reads a program's ops eight at a time; the compiled-op
 // buffers carry this many entries of padding after the last program.
 constexpr int kOpPad = 8;
@@ -72,8 +82,8 @@ enum StateWord : int {
   kStReplayElite = 3,   // 1: survival decisions are supplied
   kStMaxDepth = 4,      // deepest stack of the compiled genomes
   kStNonFinite = 5,     // set when X or y holds NaN / Inf
-  kStDeepCount = 6,     // programs that need more than kShallowSlots LDS values
-  kStWords = 8
+  kStList0 = 6,         // kLists words: the number of programs in each stack-need list
+  kStWords = 12
 };
 
 // Everything a kernel needs to know about one run; lives in the workspace.
@@ -95,7 +105,7 @@ struct RunDev {
   double* opv;              // [m + r][k] + kOpPad
   int32_t* nops;            // [m + r]
   int32_t* need;            // LDS stack values per lane each program needs, [m + r]
-  int32_t* deep;            // programs with need > kShallowSlots, [m + r] (kStDeepCount used)
+  int32_t* lists;           // programs by stack need, [kLists][m + r] (counts in kStList0 ..)
   int32_t* state;           // [kStWords]
   double* ls;               // local search: (alpha, beta) of every individual, [gmax + 1][m][2]
   double* tsum;             // local search: sum t and sum t^2 over train, then over test cases
@@ -182,17 +192,16 @@ hipError_t launch_set_state(const RunDev* d_runs, int32_t n_runs, int32_t word, 
                             hipStream_t s);
 hipError_t launch_genome(const RunDev* d_runs, const Params& p, hipStream_t s);
 hipError_t launch_compile(const RunDev* d_runs, const Params& p, hipStream_t s);
-// Interpreter passes: each takes the programs with lo < need <= slots,
-// from every program (deep_max < 0) or from each run's deep list (at most
-// deep_max programs per run).  launch_interpret: two cases per lane, any
-// slots up to kMaxLdsSlots; launch_interpret_wide: four cases per lane,
-// slots kShallowSlots or kWideDeepSlots, for runs whose X is smaller than
-// 2 GiB.
+// Interpreter passes: each takes the programs of stack-need list `list` (at
+// most `progs` per run) with lo < need <= slots.  launch_interpret: two
+// cases per lane, any slots up to kMaxLdsSlots; launch_interpret_wide: four
+// cases per lane, slots one of kListSlots, for handles whose runs each have
+// an X smaller than 2 GiB.
 hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_blocks, int lo, int slots,
-                            int32_t deep_max, hipStream_t s);
+                            int list, int32_t progs, hipStream_t s);
 hipError_t launch_interpret_wide(const RunDev* d_runs, const Params& p, int64_t case_blocks, int lo, int slots,
-                                 int32_t deep_max, hipStream_t s);
-// Third pass: every program on a deep list whose need exceeds kMaxLdsSlots,
+                                 int list, int32_t progs, hipStream_t s);
+// Last pass: every program of the last list whose need exceeds kMaxLdsSlots,
 // with its stack in `spill` (kSpillWaves columns of slots x 2 x 64 doubles).
 hipError_t launch_interpret_spill(const RunDev* d_runs, const Params& p, double* spill, int slots,
                                   hipStream_t s);

@@ -95,7 +95,8 @@ __global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs
   ops[last] = kOpEnd;
   const int need = deepest > 2 ? deepest - 2 : 0;  // the top two values live in registers
   R.need[prog] = need;
-  if (need > kShallowSlots) R.deep[atomicAdd(&R.state[kStDeepCount], 1)] = prog;
+  const int b = list_of(need);
+  R.lists[(int64_t)b * (p.m + p.r) + atomicAdd(&R.state[kStList0 + b], 1)] = prog;
   atomicMax(&R.state[kStMaxDepth], deepest);
 }
 
@@ -392,19 +393,18 @@ __device__ __forceinline__ void store_program(const RunDev& R, const Params& p, 
 }
 
 // ComputeSemantics(P) and ComputeSemantics(R) (Algorithm 1).  A block takes
-// one block of 128 cases of one run and a group of programs; each wave
-// interprets kInterpProgsPerWave programs on the block's cases.  The LDS
-// stack column of a wave bounds how many waves a CU holds, and the kernel
-// is latency-bound, so it runs in two passes: every program whose stack
-// fits in kShallowSlots LDS values, then (deep_pass) the run's list of
-// deeper programs with a column sized for the deepest.  Pool rows
+// one block of 128 cases of one run and a group of programs of one
+// stack-need list; each wave interprets kInterpProgsPerWave programs on the
+// block's cases.  The LDS stack column of a wave bounds how many waves a CU
+// holds, and the kernel is latency-bound, so each list runs in a pass of
+// its own with a column sized for it.  Pool rows
 // are squashed by the logistic function (the random functions R_u of GSM,
 // Section 2) before storage.  Padding columns are written as exact zeros.
 // (Staging the case block's features in LDS was slower: the tile cut the
 // number of resident waves more than it saved in L2 reads.)
 template <typename T>
 __global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ runs, Params p, int32_t pgroups,
-                                                   int lo, int slots, int deep_pass) {
+                                                   int lo, int slots, int list) {
   extern __shared__ double lds[];
   const int lane = threadIdx.x & 63;
   const int wave = uni(threadIdx.x >> 6);
@@ -426,15 +426,10 @@ __global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ ru
   }
   for (int j = 0; j < kInterpProgsPerWave; ++j) {
     const int idx = (pg * kInterpProgsPerWave + j) * W + wave;
-    int prog;
-    if (deep_pass) {
-      if (idx >= uni(cload(&R.state[kStDeepCount]))) break;
-      prog = uni(cload(&R.deep[idx]));
-    } else {
-      if (idx >= rows) break;
-      prog = idx;
-    }
-    // this pass takes the programs with lo < need <= slots
+    if (idx >= uni(cload(&R.state[kStList0 + list]))) break;
+    const int prog = uni(cload(&R.lists[(int64_t)list * rows + idx]));
+    // this pass takes the programs with lo < need <= slots (the list holds
+    // no other; the test keeps every stack inside the column regardless)
     const int need = uni(cload(&R.need[prog]));
     if (need <= lo || need > slots) continue;
     double out[kInterpV];
@@ -446,9 +441,9 @@ __global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ ru
 
 // ComputeSemantics with eval_program_wide: a block of 4 waves takes one
 // block of kWideTile cases of one run (lanes own kWideV cases each) and
-// 4 programs, one per wave; a wave's LDS column holds SLOTS stack values per
-// lane.  The pass takes the programs with lo < need <= SLOTS, from all
-// programs or (deep_pass) from the run's deep list.  Every lane's byte
+// 4 programs of one stack-need list, one per wave; a wave's LDS column holds
+// SLOTS stack values per lane.  The pass takes the list's programs with
+// lo < need <= SLOTS.  Every lane's byte
 // offset into a feature row (its case, or the last column for lanes past
 // it, whose values are never stored) fits in 32 bits, and so does a feature
 // row's offset in X: the runtime uses this kernel only when every run's X
@@ -459,7 +454,7 @@ constexpr int kWideWaves = 4;
 
 template <typename T, int SLOTS>
 __global__ __launch_bounds__(kWideWaves * kWave) void k_interpret_wide(const RunDev* __restrict__ runs, Params p,
-                                                                        int32_t pgroups, int lo, int deep_pass) {
+                                                                        int32_t pgroups, int lo, int list) {
   __shared__ double lds[kWideWaves * SLOTS * kWideV * kWave];
   const int lane = threadIdx.x & 63;
   const int wave = uni(threadIdx.x >> 6);
@@ -469,14 +464,8 @@ __global__ __launch_bounds__(kWideWaves * kWave) void k_interpret_wide(const Run
   const RunDev& R = runs[run];
   const int64_t cb = cbg - R.cblk0w;
   const int idx = pg * kWideWaves + wave;
-  int prog;
-  if (deep_pass) {
-    if (idx >= uni(cload(&R.state[kStDeepCount]))) return;
-    prog = uni(cload(&R.deep[idx]));
-  } else {
-    if (idx >= p.m + p.r) return;
-    prog = idx;
-  }
+  if (idx >= uni(cload(&R.state[kStList0 + list]))) return;
+  const int prog = uni(cload(&R.lists[(int64_t)list * (p.m + p.r) + idx]));
   const int need = uni(cload(&R.need[prog]));
   if (need <= lo || need > SLOTS) return;
   int64_t col[kWideV];
@@ -494,8 +483,8 @@ __global__ __launch_bounds__(kWideWaves * kWave) void k_interpret_wide(const Run
   store_program<T, kWideV>(R, p, prog, col, ok, out);
 }
 
-// Third pass: the deep-list programs whose stack exceeds the largest LDS
-// column (need > kMaxLdsSlots).  kSpillWaves waves, one per block, each own
+// Last pass: the programs of the last list whose stack exceeds the largest
+// LDS column (need > kMaxLdsSlots).  kSpillWaves waves, one per block, each own
 // a column of `slots` x kInterpV x 64 doubles in `spill` (lane-strided as in
 // LDS, so every stack access is one coalesced 512-byte row) and sweep the
 // (program, case block) tasks of every run in turn.
@@ -507,13 +496,14 @@ __global__ __launch_bounds__(64) void k_interpret_spill(const RunDev* __restrict
   double* stk = spill + (int64_t)w * slots * kInterpV * kWave;
   for (int run = 0; run < p.n_runs; ++run) {
     const RunDev& R = runs[run];
-    const int cnt = uni(cload(&R.state[kStDeepCount]));
+    const int cnt = uni(cload(&R.state[kStList0 + kLists - 1]));
+    const int32_t* list = R.lists + (int64_t)(kLists - 1) * (p.m + p.r);
     const int64_t cblocks = (R.ld + kInterpTile - 1) / kInterpTile;
     const int64_t tasks = (int64_t)cnt * cblocks;
     for (int64_t t = w; t < tasks; t += gridDim.x) {
       const int j = (int)(t / cblocks);
       const int64_t cb = t - (int64_t)j * cblocks;
-      const int prog = uni(cload(&R.deep[j]));
+      const int prog = uni(cload(&list[j]));
       const int need = uni(cload(&R.need[prog]));
       if (need <= kMaxLdsSlots || need > slots) continue;  // LDS passes took it; never beyond the column
       int64_t col[kInterpV];
@@ -614,54 +604,54 @@ hipError_t launch_compile(const RunDev* d_runs, const Params& p, hipStream_t s) 
 }
 
 hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_blocks, int lo, int slots,
-                            int32_t deep_max, hipStream_t s) {
+                            int list, int32_t progs, hipStream_t s) {
   if (slots < 1) slots = 1;
   if (slots > kMaxLdsSlots) return hipErrorInvalidValue;  // deeper stacks take the spill pass
-  if (deep_max == 0) return hipSuccess;
+  if (list < 0 || list >= kLists) return hipErrorInvalidValue;
+  if (progs <= 0) return hipSuccess;
   // one LDS stack column block per wave, at most 64 KiB per block
   const int waves = interp_waves(slots);
   const size_t shmem = (size_t)waves * slots * kInterpV * kWave * sizeof(double);
-  const int progs = deep_max > 0 ? deep_max : p.m + p.r;
   const int32_t pgroups = (progs + waves * kInterpProgsPerWave - 1) / (waves * kInterpProgsPerWave);
   // any workspace that fits on the device keeps this far below the limit
   if (case_blocks * pgroups > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)(case_blocks * pgroups)), block(waves * kWave);
-  const int deep_pass = deep_max > 0 ? 1 : 0;
   if (p.precision == GSGP_FP64)
-    hipLaunchKernelGGL((k_interpret<double>), grid, block, shmem, s, d_runs, p, pgroups, lo, slots, deep_pass);
+    hipLaunchKernelGGL((k_interpret<double>), grid, block, shmem, s, d_runs, p, pgroups, lo, slots, list);
   else
-    hipLaunchKernelGGL((k_interpret<float>), grid, block, shmem, s, d_runs, p, pgroups, lo, slots, deep_pass);
+    hipLaunchKernelGGL((k_interpret<float>), grid, block, shmem, s, d_runs, p, pgroups, lo, slots, list);
   return hipGetLastError();
 }
 
 template <typename T, int SLOTS>
-void launch_wide_as(const RunDev* d_runs, const Params& p, dim3 grid, int32_t pgroups, int lo, int deep_pass,
+void launch_wide_as(const RunDev* d_runs, const Params& p, dim3 grid, int32_t pgroups, int lo, int list,
                     hipStream_t s) {
   hipLaunchKernelGGL((k_interpret_wide<T, SLOTS>), grid, dim3(kWideWaves * kWave), 0, s, d_runs, p, pgroups, lo,
-                     deep_pass);
+                     list);
+}
+
+template <typename T>
+hipError_t launch_wide_slots(const RunDev* d_runs, const Params& p, dim3 grid, int32_t pgroups, int lo, int slots,
+                             int list, hipStream_t s) {
+  switch (slots) {
+    case kListSlots[0]: launch_wide_as<T, kListSlots[0]>(d_runs, p, grid, pgroups, lo, list, s); break;
+    case kListSlots[1]: launch_wide_as<T, kListSlots[1]>(d_runs, p, grid, pgroups, lo, list, s); break;
+    case kListSlots[2]: launch_wide_as<T, kListSlots[2]>(d_runs, p, grid, pgroups, lo, list, s); break;
+    case kListSlots[3]: launch_wide_as<T, kListSlots[3]>(d_runs, p, grid, pgroups, lo, list, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_interpret_wide(const RunDev* d_runs, const Params& p, int64_t case_blocks, int lo, int slots,
-                                 int32_t deep_max, hipStream_t s) {
-  if (deep_max == 0) return hipSuccess;
-  if (slots != kShallowSlots && slots != kWideDeepSlots) return hipErrorInvalidValue;
-  const int progs = deep_max > 0 ? deep_max : p.m + p.r;
+                                 int list, int32_t progs, hipStream_t s) {
+  if (list < 0 || list >= kLists) return hipErrorInvalidValue;
+  if (progs <= 0) return hipSuccess;
   const int32_t pgroups = (progs + kWideWaves - 1) / kWideWaves;
   if (case_blocks * pgroups > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)(case_blocks * pgroups));
-  const int deep_pass = deep_max > 0 ? 1 : 0;
-  if (p.precision == GSGP_FP64) {
-    if (slots == kShallowSlots)
-      launch_wide_as<double, kShallowSlots>(d_runs, p, grid, pgroups, lo, deep_pass, s);
-    else
-      launch_wide_as<double, kWideDeepSlots>(d_runs, p, grid, pgroups, lo, deep_pass, s);
-  } else {
-    if (slots == kShallowSlots)
-      launch_wide_as<float, kShallowSlots>(d_runs, p, grid, pgroups, lo, deep_pass, s);
-    else
-      launch_wide_as<float, kWideDeepSlots>(d_runs, p, grid, pgroups, lo, deep_pass, s);
-  }
-  return hipGetLastError();
+  return p.precision == GSGP_FP64 ? launch_wide_slots<double>(d_runs, p, grid, pgroups, lo, slots, list, s)
+                                  : launch_wide_slots<float>(d_runs, p, grid, pgroups, lo, slots, list, s);
 }
 
 hipError_t launch_interpret_spill(const RunDev* d_runs, const Params& p, double* spill, int slots,

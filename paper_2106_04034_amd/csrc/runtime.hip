@@ -79,7 +79,7 @@ size_t storage_bytes(int32_t precision) { return precision == GSGP_FP64 ? 8 : 4;
 struct RunPlan {
   int64_t n_train, n_test, tr_pad, te_pad, ld;
   int32_t l, nch_tr, nch_te;
-  size_t X, y, S0, S1, sigR, part, F0, F1, Ft0, Ft1, rec, stats, elite_in, code, cval, ops, opv, nops, need, deep;
+  size_t X, y, S0, S1, sigR, part, F0, F1, Ft0, Ft1, rec, stats, elite_in, code, cval, ops, opv, nops, need, lists;
   size_t ls, tsum;
   size_t end;
 };
@@ -200,7 +200,7 @@ gsgp_status make_plan(const gsgp_config* c, const gsgp_run* runs, int32_t n_runs
     p.opv = take_at(8 * ((m + r) * k + kOpPad), i, "compiled constants");
     p.nops = take_at(4 * (m + r), i, "program lengths");
     p.need = take_at(4 * (m + r), i, "program stack needs");
-    p.deep = take_at(4 * (m + r), i, "deep program list");
+    p.lists = take_at(4 * kLists * (m + r), i, "program lists by stack need");
     // local search: the scaling table of every generation and the target sums
     p.ls = take_at(ls ? sizeof(double) * 2 * (G + 1) * m : 0, i, "scaling table");
     p.tsum = take_at(ls ? sizeof(double) * 4 : 0, i, "target sums");
@@ -547,7 +547,7 @@ gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_ru
     R.opv = (double*)(ws + q.opv);
     R.nops = (int32_t*)(ws + q.nops);
     R.need = (int32_t*)(ws + q.need);
-    R.deep = (int32_t*)(ws + q.deep);
+    R.lists = (int32_t*)(ws + q.lists);
     R.ls = (double*)(ws + q.ls);
     R.tsum = (double*)(ws + q.tsum);
     R.state = state + (size_t)kStWords * i;
@@ -635,28 +635,27 @@ gsgp_status gsgp_destroy(gsgp_handle* h) {
 
 namespace {
 
-// ComputeSemantics of every compiled program, in passes by the stack depth
-// a program needs (h->slots is the deepest): every program that fits a
-// small LDS column, then the deep list in larger columns, then the programs
-// beyond any LDS column (spill stacks).  Handles whose runs each have an X
-// smaller than 2 GiB (all practical ones) use the four-cases-per-lane kernel
-// for the first two passes.
-hipError_t interpret_all(gsgp_handle* h, int32_t deep_max, hipStream_t s) {
+// ComputeSemantics of every compiled program, in one pass per stack-need
+// list, each with the smallest LDS column that holds its programs (more
+// resident waves for the shallow lists): the first kLists - 1 lists with the
+// four-cases-per-lane kernel (handles whose runs each have an X smaller
+// than 2 GiB, all practical ones) or else the two-cases-per-lane kernel,
+// then the last list with columns up to kMaxLdsSlots, then the programs
+// beyond any LDS column (spill stacks).  counts[b]: the longest list b over
+// the runs.
+hipError_t interpret_all(gsgp_handle* h, const int32_t (&counts)[kLists], hipStream_t s) {
   const Params& p = h->params;
-  hipError_t e;
-  int done;  // programs with need <= done are evaluated
-  if (h->interp_wide) {
-    e = launch_interpret_wide(h->runs_d, p, h->interp_tasks_w, -1, kShallowSlots, -1, s);
-    if (e == hipSuccess && h->slots > kShallowSlots)
-      e = launch_interpret_wide(h->runs_d, p, h->interp_tasks_w, kShallowSlots, kWideDeepSlots, deep_max, s);
-    done = kWideDeepSlots;
-  } else {
-    constexpr int kFirst = 5;  // the two-cases-per-lane kernel's first column
-    e = launch_interpret(h->runs_d, p, h->interp_tasks, -1, std::min(h->slots, kFirst), -1, s);
-    done = kFirst;
+  hipError_t e = hipSuccess;
+  for (int b = 0; b < kLists - 1 && e == hipSuccess; ++b) {
+    const int lo = b == 0 ? -1 : kListSlots[b - 1];
+    if (h->interp_wide)
+      e = launch_interpret_wide(h->runs_d, p, h->interp_tasks_w, lo, kListSlots[b], b, counts[b], s);
+    else
+      e = launch_interpret(h->runs_d, p, h->interp_tasks, lo, kListSlots[b], b, counts[b], s);
   }
-  if (e == hipSuccess && h->slots > done)
-    e = launch_interpret(h->runs_d, p, h->interp_tasks, done, std::min(h->slots, kMaxLdsSlots), deep_max, s);
+  if (e == hipSuccess && h->slots > kListSlots[kLists - 2])
+    e = launch_interpret(h->runs_d, p, h->interp_tasks, kListSlots[kLists - 2], std::min(h->slots, kMaxLdsSlots),
+                         kLists - 1, counts[kLists - 1], s);
   if (e == hipSuccess && h->slots > kMaxLdsSlots)
     e = launch_interpret_spill(h->runs_d, p, (double*)(h->ws + h->plan.spill), h->slots, s);
   return e;
@@ -682,8 +681,9 @@ gsgp_status eval_impl(gsgp_handle* h, const int32_t* h_codes, const double* h_co
     }
   }
   if (ev) HIPCHK(h, hipEventRecord(ev[0], h->stream));
-  for (int32_t w : {kStGen, kStDone, kStReplaySelect, kStReplayElite, kStMaxDepth, kStDeepCount})
+  for (int32_t w : {kStGen, kStDone, kStReplaySelect, kStReplayElite, kStMaxDepth})
     HIPCHK(h, launch_set_state(h->runs_d, h->n_runs, w, 0, h->stream));
+  for (int32_t b = 0; b < kLists; ++b) HIPCHK(h, launch_set_state(h->runs_d, h->n_runs, kStList0 + b, 0, h->stream));
   if (h_codes) {
     for (int32_t r = 0; r < h->n_runs; ++r) {
       HIPCHK(h, hipMemcpyAsync(h->runs_h[r].code, h_codes + r * per, 4 * per, hipMemcpyHostToDevice, h->stream));
@@ -697,10 +697,10 @@ gsgp_status eval_impl(gsgp_handle* h, const int32_t* h_codes, const double* h_co
   int32_t* state = (int32_t*)(h->ws + h->plan.state);
   HIPCHK(h, hipMemcpyAsync(h->pinned, state, sizeof(int32_t) * kStWords * h->n_runs, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  int32_t deepest = 0, deep_max = 0;
+  int32_t deepest = 0, counts[kLists] = {0, 0, 0, 0, 0};
   for (int32_t r = 0; r < h->n_runs; ++r) {
     deepest = std::max(deepest, h->pinned[kStWords * r + kStMaxDepth]);
-    deep_max = std::max(deep_max, h->pinned[kStWords * r + kStDeepCount]);
+    for (int32_t b = 0; b < kLists; ++b) counts[b] = std::max(counts[b], h->pinned[kStWords * r + kStList0 + b]);
   }
   h->slots = std::max(1, deepest - 2);  // the top two values live in registers
   // the deepest stack up to a genome's last valid function is at most k - 1
@@ -709,7 +709,7 @@ gsgp_status eval_impl(gsgp_handle* h, const int32_t* h_codes, const double* h_co
     h->poisoned = true;
     return fail(GSGP_ERR_STATE, "compiled stack depth %d exceeds the bound for genomes of %d genes", deepest, p.k);
   }
-  HIPCHK(h, interpret_all(h, deep_max, h->stream));
+  HIPCHK(h, interpret_all(h, counts, h->stream));
 
   if (ev) HIPCHK(h, hipEventRecord(ev[2], h->stream));
   if (p.ls) HIPCHK(h, launch_target_sums(h->runs_d, p, h->stream));  // and generation 0's scaling
@@ -1471,7 +1471,7 @@ struct CkptHeader {
   uint32_t seed, result_flags;
   double p_crossover, mutation_step, p_function, p_feature, erc_lo, erc_hi;
 };
-constexpr int32_t kCkptVersion = 5;  // 5: genomes recompiled on load
+constexpr int32_t kCkptVersion = 6;  // 5: genomes recompiled on load; 6: twelve state words per run
 static_assert(sizeof(CkptHeader) == 112, "no padding between header fields");
 
 struct CkptPiece {
@@ -1620,7 +1620,7 @@ gsgp_status gsgp_checkpoint_load(gsgp_handle* h, const void* h_buf, size_t bytes
   }
   // compile the loaded genomes for this workspace (the depth words restart)
   HIPCHK(h, launch_set_state(h->runs_d, h->n_runs, kStMaxDepth, 0, h->stream));
-  HIPCHK(h, launch_set_state(h->runs_d, h->n_runs, kStDeepCount, 0, h->stream));
+  for (int32_t b = 0; b < kLists; ++b) HIPCHK(h, launch_set_state(h->runs_d, h->n_runs, kStList0 + b, 0, h->stream));
   HIPCHK(h, launch_compile(h->runs_d, h->params, h->stream));
   int32_t* state = (int32_t*)(h->ws + h->plan.state);
   HIPCHK(h, hipMemcpyAsync(h->pinned, state, sizeof(int32_t) * kStWords * h->n_runs, hipMemcpyDeviceToHost, h->stream));
