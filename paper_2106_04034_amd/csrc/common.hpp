@@ -83,6 +83,7 @@ enum StateWord : int {
   kStMaxDepth = 4,      // deepest stack of the compiled genomes
   kStNonFinite = 5,     // set when X or y holds NaN / Inf
   kStList0 = 6,         // kLists words: the number of programs in each stack-need list
+  kStXBig = 11,         // set when X holds a value beyond 2^128 in magnitude
   kStWords = 12
 };
 
@@ -103,6 +104,7 @@ struct RunDev {
   double* cval;             // [m + r][k]
   int32_t* ops;             // compiled genomes, [m + r][k] + kOpPad
   double* opv;              // [m + r][k] + kOpPad
+  double* opy;              // per compiled op: a constant divisor's refined reciprocal, else 0, [m + r][k] + kOpPad
   int32_t* nops;            // [m + r]
   int32_t* need;            // LDS stack values per lane each program needs, [m + r]
   int32_t* lists;           // programs by stack need, [kLists][m + r] (counts in kStList0 ..)
@@ -116,7 +118,7 @@ struct RunDev {
   int32_t nch_tr, nch_te, nch;  // chunks per segment and in total
   uint32_t run_id;
   int32_t surv_blk0, surv_blks; // survival kernel blocks of this run
-  int32_t pad0;
+  int32_t x_big;            // X holds a value beyond 2^128 in magnitude (no short division by features)
   int64_t vary_task0;       // first task of this run in the variation launch
   int64_t cblk0;            // first 128-case block of this run (interpreter)
   int64_t cblk0w;           // first 256-case block of this run (wide interpreter)

@@ -27,6 +27,35 @@ namespace {
 // bit 1 set (a push uses only bit 0).
 constexpr int32_t kOpEnd = 2;
 
+// Division (the protected division of Section 2.2: a / b where |b| >= 1e-6).
+// The FP64 division the compiler emits is a reciprocal estimate refined by
+// two Newton-Raphson steps, a quotient, and one correction by its residual,
+// all with FMA, inside an operand range scaling and a special-case fix-up.
+// When |b| lies in [1e-6, 2^128], |a| >= 2^-700 and the quotient is at most
+// 2^127 in magnitude, no operand, reciprocal or quotient comes near either
+// end of the exponent range, so the scaling and the fix-up leave every value
+// as it is and the core steps alone (div_recip, div_short) give the same
+// bits.  The reciprocal depends on b alone: for a constant divisor the
+// compile step refines it once.
+constexpr double kDivShortMinDivisor = 1e-6;
+constexpr double kDivShortMaxDivisor = 0x1p128;
+constexpr double kDivShortMinDividend = 0x1p-700;
+constexpr double kDivShortMaxQuotient = 0x1p127;
+
+__device__ __forceinline__ double div_recip(double b) {
+  double y = __builtin_amdgcn_rcp(b);
+  double e = fma(-b, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-b, y, 1.0);
+  return fma(y, e, y);
+}
+
+__device__ __forceinline__ double div_short(double a, double b, double y) {
+  const double q = a * y;
+  const double r = fma(-b, q, a);
+  return fma(r, y, q);
+}
+
 // Compile a genome: drop the functions the stack machine would skip (fewer
 // than two operands) and everything after the last function that runs, and
 // store each op's stack depth so the interpreter needs no depth counter.
@@ -43,6 +72,7 @@ __global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs
   const double* cval = R.cval + (int64_t)prog * p.k;
   int32_t* ops = R.ops + (int64_t)prog * p.k;
   double* opv = R.opv + (int64_t)prog * p.k;
+  double* opy = R.opy + (int64_t)prog * p.k;
   // deepest: the deepest stack up to the last valid function; pushes after
   // it are dropped and never run, so they do not count
   int depth = 0, n = 0, last = 0, deepest = 0, peak = 0;
@@ -58,12 +88,14 @@ __global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs
       ops[n] = prev;
       // the address of the feature's row in this run's X, bit for bit (see eval_program)
       opv[n] = __longlong_as_double((long long)(R.X + (int64_t)c * R.ld));
+      opy[n] = 0.0;
       ++n;
       ++depth;
     } else if (c == -5) {
       prev = (kClsPush << 2) | kPushConst | dfield;
       ops[n] = prev;
       opv[n] = cval[q];
+      opy[n] = 0.0;
       ++n;
       ++depth;
     } else {
@@ -76,10 +108,18 @@ __global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs
         const int cls = (prev & 3) == kPushConst ? kClsConst : kClsFeature;
         prev = (prev & ~0xF) | (cls << 2) | fn;
         ops[n - 1] = prev;
+        if (cls == kClsConst && fn == kFnDiv) {
+          // a constant divisor in the short division's range: its reciprocal
+          // refinement, once (0 selects the full division)
+          const double b = opv[n - 1];
+          const double ab = fabs(b);
+          opy[n - 1] = ab >= kDivShortMinDivisor && ab <= kDivShortMaxDivisor ? div_recip(b) : 0.0;
+        }
       } else {
         prev = (kClsStack << 2) | fn | dfield;
         ops[n] = prev;
         opv[n] = 0.0;
+        opy[n] = 0.0;
         ++n;
       }
       --depth;
@@ -95,9 +135,46 @@ __global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs
   ops[last] = kOpEnd;
   const int need = deepest > 2 ? deepest - 2 : 0;  // the top two values live in registers
   R.need[prog] = need;
-  const int b = list_of(need);
-  R.lists[(int64_t)b * (p.m + p.r) + atomicAdd(&R.state[kStList0 + b], 1)] = prog;
   atomicMax(&R.state[kStMaxDepth], deepest);
+}
+
+// Files each run's programs into the stack-need lists, each list in order
+// of decreasing length (a counting sort on kOrderBins length bins, one block
+// per run): the programs of one interpreter block then run for about as
+// long as each other, and the long ones start first.  The order within a
+// bin is arbitrary; semantics do not depend on it.
+constexpr int kOrderBins = 256;
+__global__ __launch_bounds__(1024) void k_order(const RunDev* __restrict__ runs, Params p, int shift) {
+  __shared__ int32_t at[kLists * kOrderBins];
+  const RunDev& R = runs[blockIdx.x];
+  const int rows = p.m + p.r;
+  auto key = [&](int prog, int& list) {
+    list = list_of(R.need[prog]);
+    return list * kOrderBins + ((p.k - R.nops[prog]) >> shift);
+  };
+  for (int i = threadIdx.x; i < kLists * kOrderBins; i += blockDim.x) at[i] = 0;
+  __syncthreads();
+  for (int prog = threadIdx.x; prog < rows; prog += blockDim.x) {
+    int list;
+    atomicAdd(&at[key(prog, list)], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < kLists) {  // bin counts to first positions, per list
+    int32_t* h = at + threadIdx.x * kOrderBins;
+    int32_t sum = 0;
+    for (int j = 0; j < kOrderBins; ++j) {
+      const int32_t c = h[j];
+      h[j] = sum;
+      sum += c;
+    }
+    R.state[kStList0 + threadIdx.x] = sum;
+  }
+  __syncthreads();
+  for (int prog = threadIdx.x; prog < rows; prog += blockDim.x) {
+    int list;
+    const int slot = atomicAdd(&at[key(prog, list)], 1);
+    R.lists[(int64_t)list * rows + slot] = prog;
+  }
 }
 
 // Evaluate one compiled program on V cases per lane (Section 2.2
@@ -257,11 +334,13 @@ __device__ __forceinline__ void eval_program(const int32_t* ops, const double* o
 // The FP64 operations and their order are those of eval_program, so results
 // are the same bits.
 template <int V, typename Stack>
-__device__ __forceinline__ void eval_program_wide(const int32_t* ops, const double* opv, const double* X,
+__device__ __forceinline__ void eval_program_wide(const int32_t* ops, const double* opv, const double* opy,
+                                                  const double* X, bool short_feature_div,
                                                   const uint32_t (&off)[V], Stack stk, int lane, double (&out)[V]) {
   constexpr int kBatch = kOpPad;
   const GSGP_CONST int32_t* cops = (const GSGP_CONST int32_t*)ops;
   const GSGP_CONST double* copv = (const GSGP_CONST double*)opv;
+  const GSGP_CONST double* copy = (const GSGP_CONST double*)opy;
   double tos[V], nos[V];
 #pragma unroll
   for (int v = 0; v < V; ++v) {
@@ -279,38 +358,78 @@ __device__ __forceinline__ void eval_program_wide(const int32_t* ops, const doub
       x[v] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(xr, (int)off[v], row, 0));
   };
   auto clamp = [](double x) { return fmin(fmax(x, -kFltMax), kFltMax); };
-  auto apply = [&](int w, const double (&b)[V]) {
-    if (w & 2) {
-      if (w & 1) {
+  // The clamp changes nothing where |x| <= FLT_MAX: one compare per case,
+  // and the min/max only when some case of the wave needs them (NaN, which
+  // finite operands never produce, takes them too).
+  auto settle = [&]() {
+    uint64_t out_of_range = 0;
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-          const bool tiny = fabs(b[v]) < 1e-6;  // protected division, as in eval_program
-          const double q = tos[v] / (tiny ? 1.0 : b[v]);
-          tos[v] = clamp(tiny ? 1.0 : q);
-        }
-      } else {
+    for (int v = 0; v < V; ++v) out_of_range |= __builtin_amdgcn_ballot_w64(!(fabs(tos[v]) <= kFltMax));
+    if (out_of_range) {
 #pragma unroll
-        for (int v = 0; v < V; ++v) tos[v] = clamp(tos[v] * b[v]);
-      }
-    } else {
-      if (w & 1) {
-#pragma unroll
-        for (int v = 0; v < V; ++v) tos[v] = clamp(tos[v] - b[v]);
-      } else {
-#pragma unroll
-        for (int v = 0; v < V; ++v) tos[v] = clamp(tos[v] + b[v]);
-      }
+      for (int v = 0; v < V; ++v) tos[v] = clamp(tos[v]);
     }
+  };
+  auto divide_full = [&](const double (&b)[V]) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const bool tiny = fabs(b[v]) < 1e-6;  // protected division, as in eval_program
+      const double q = tos[v] / (tiny ? 1.0 : b[v]);
+      tos[v] = clamp(tiny ? 1.0 : q);
+    }
+  };
+  // The short division (div_short): taken when every case of the wave has
+  // |b| >= 1e-6 (with y its reciprocal refinement), |tos| >= 2^-700 and a
+  // quotient of at most 2^127, where it gives the bits of the full one.
+  auto divide = [&](const double (&b)[V], const double (&y)[V], uint64_t bad) {
+    double q[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      q[v] = div_short(tos[v], b[v], y[v]);
+      bad |= __builtin_amdgcn_ballot_w64(!(fabs(tos[v]) >= kDivShortMinDividend)) |
+             __builtin_amdgcn_ballot_w64(!(fabs(q[v]) <= kDivShortMaxQuotient));
+    }
+    if (bad) {
+      divide_full(b);
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) tos[v] = q[v];
+    }
+  };
+  // a divisor from the registers: every case refines its own reciprocal
+  auto divide_by = [&](const double (&b)[V]) {
+    double y[V];
+    uint64_t bad = 0;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      y[v] = div_recip(b[v]);
+      bad |= __builtin_amdgcn_ballot_w64(!(fabs(b[v]) >= kDivShortMinDivisor));
+    }
+    divide(b, y, bad);
+  };
+  auto arith = [&](int w, const double (&b)[V]) {
+    if (w & 2) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) tos[v] = tos[v] * b[v];
+    } else if (w & 1) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) tos[v] = tos[v] - b[v];
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) tos[v] = tos[v] + b[v];
+    }
+    settle();
   };
   for (int j0 = 0;; j0 += kBatch) {
     int wv[kBatch];
-    double cv[kBatch];
+    double cv[kBatch], yv[kBatch];
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
-      // one batch per two scalar loads; reads past a program's end word
+      // one batch per three scalar loads; reads past a program's end word
       // stay inside the buffers' padding and are never used
       wv[u] = cops[j0 + u];
       cv[u] = copv[j0 + u];
+      yv[u] = copy[j0 + u];
     }
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
@@ -320,10 +439,27 @@ __device__ __forceinline__ void eval_program_wide(const int32_t* ops, const doub
         if (w & 4) {
 #pragma unroll
           for (int v = 0; v < V; ++v) b[v] = cv[u];
+          if ((w & 3) != kFnDiv) {
+            arith(w, b);
+          } else if (__double_as_longlong(yv[u]) != 0) {
+            // the compile step refined the constant's reciprocal (and
+            // checked the constant's range)
+            double y[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) y[v] = yv[u];
+            divide(b, y, 0);
+          } else {
+            divide_full(b);
+          }
         } else {
           feature(cv[u], b);
+          if ((w & 3) != kFnDiv)
+            arith(w, b);
+          else if (short_feature_div)
+            divide_by(b);
+          else
+            divide_full(b);
         }
-        apply(w, b);
       } else if (w & 4) {  // tos = f(nos, tos), then the new nos from LDS
         double b[V];
 #pragma unroll
@@ -331,7 +467,11 @@ __device__ __forceinline__ void eval_program_wide(const int32_t* ops, const doub
           b[v] = tos[v];
           tos[v] = nos[v];
         }
-        apply(w, b);
+        // b is the output of a function, so |b| <= FLT_MAX
+        if ((w & 3) != kFnDiv)
+          arith(w, b);
+        else
+          divide_by(b);
         const int d = (w >> 4) & kOpDepthMax;
         if (d >= 3) {
 #pragma unroll
@@ -439,18 +579,21 @@ __global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ ru
   }
 }
 
-// ComputeSemantics with eval_program_wide: a block of 4 waves takes one
-// block of kWideTile cases of one run (lanes own kWideV cases each) and
-// 4 programs of one stack-need list, one per wave; a wave's LDS column holds
-// SLOTS stack values per lane.  The pass takes the list's programs with
-// lo < need <= SLOTS.  Every lane's byte
+// ComputeSemantics with eval_program_wide: a block of kWideWaves waves takes
+// one block of kWideTile cases of one run (lanes own kWideV cases each) and
+// kWideWaves programs of one stack-need list, one per wave; a wave's LDS
+// column holds SLOTS stack values per lane.  The pass takes the list's
+// programs with lo < need <= SLOTS.  One wave per block: a block's LDS and
+// slot are released as soon as its one program is done, where four waves
+// of unequal programs held them until the longest ended (3 % faster at the
+// Section 3.1 shape, 7 % on 256 small runs).  Every lane's byte
 // offset into a feature row (its case, or the last column for lanes past
 // it, whose values are never stored) fits in 32 bits, and so does a feature
 // row's offset in X: the runtime uses this kernel only when every run's X
 // is smaller than 2 GiB.
 constexpr int kWideV = 4;
 constexpr int kWideTile = kWave * kWideV;
-constexpr int kWideWaves = 4;
+constexpr int kWideWaves = 1;
 
 template <typename T, int SLOTS>
 __global__ __launch_bounds__(kWideWaves * kWave) void k_interpret_wide(const RunDev* __restrict__ runs, Params p,
@@ -478,8 +621,8 @@ __global__ __launch_bounds__(kWideWaves * kWave) void k_interpret_wide(const Run
     off[v] = (uint32_t)((ok[v] ? col[v] : R.ld - 1) * (int64_t)sizeof(double));
   }
   double out[kWideV];
-  eval_program_wide<kWideV>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k, R.X, off,
-                            (LdsStack)(lds + wave * SLOTS * kWideV * kWave), lane, out);
+  eval_program_wide<kWideV>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k, R.opy + (int64_t)prog * p.k,
+                            R.X, uni(R.x_big) == 0, off, (LdsStack)(lds + wave * SLOTS * kWideV * kWave), lane, out);
   store_program<T, kWideV>(R, p, prog, col, ok, out);
 }
 
@@ -600,6 +743,12 @@ inline int interp_waves(int slots) {
 hipError_t launch_compile(const RunDev* d_runs, const Params& p, hipStream_t s) {
   const int32_t total = p.n_runs * (p.m + p.r);
   hipLaunchKernelGGL(k_compile, dim3(blocks_for(total, 256)), dim3(256), 0, s, d_runs, p, total);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // length bins: (k - length) >> shift < kOrderBins for lengths 0 .. k
+  int shift = 0;
+  while ((p.k >> shift) >= kOrderBins) ++shift;
+  hipLaunchKernelGGL(k_order, dim3(p.n_runs), dim3(1024), 0, s, d_runs, p, shift);
   return hipGetLastError();
 }
 

@@ -89,16 +89,18 @@ __global__ __launch_bounds__(256) void k_prep(const RunDev* __restrict__ runs, P
     ys = src[4 * run + 3];
     row = col - R.tr_pad;
   }
-  bool bad = false;
+  bool bad = false, big = false;
   for (int f = 0; f < R.l; ++f) {
     const double v = (row >= 0) ? Xs[row * R.l + f] : 0.0;
     bad |= !isfinite(v);
+    big |= fabs(v) > 0x1p128;
     R.X[(int64_t)f * R.ld + col] = v;
   }
   const double yv = (row >= 0) ? ys[row] : 0.0;
   bad |= !isfinite(yv) || fabs(yv) > kFltMax;
   ((T*)R.y)[col] = (T)yv;
   if (bad) atomicOr(&R.state[kStNonFinite], 1);
+  if (big) atomicOr(&R.state[kStXBig], 1);
 }
 
 // ---------------------------------------------------------------------------

@@ -79,7 +79,7 @@ size_t storage_bytes(int32_t precision) { return precision == GSGP_FP64 ? 8 : 4;
 struct RunPlan {
   int64_t n_train, n_test, tr_pad, te_pad, ld;
   int32_t l, nch_tr, nch_te;
-  size_t X, y, S0, S1, sigR, part, F0, F1, Ft0, Ft1, rec, stats, elite_in, code, cval, ops, opv, nops, need, lists;
+  size_t X, y, S0, S1, sigR, part, F0, F1, Ft0, Ft1, rec, stats, elite_in, code, cval, ops, opv, opy, nops, need, lists;
   size_t ls, tsum;
   size_t end;
 };
@@ -198,6 +198,7 @@ gsgp_status make_plan(const gsgp_config* c, const gsgp_run* runs, int32_t n_runs
     p.cval = take_at(8 * (m + r) * k, i, "genome constants");
     p.ops = take_at(4 * ((m + r) * k + kOpPad), i, "compiled ops");
     p.opv = take_at(8 * ((m + r) * k + kOpPad), i, "compiled constants");
+    p.opy = take_at(8 * ((m + r) * k + kOpPad), i, "compiled reciprocals");
     p.nops = take_at(4 * (m + r), i, "program lengths");
     p.need = take_at(4 * (m + r), i, "program stack needs");
     p.lists = take_at(4 * kLists * (m + r), i, "program lists by stack need");
@@ -545,6 +546,7 @@ gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_ru
     R.cval = (double*)(ws + q.cval);
     R.ops = (int32_t*)(ws + q.ops);
     R.opv = (double*)(ws + q.opv);
+    R.opy = (double*)(ws + q.opy);
     R.nops = (int32_t*)(ws + q.nops);
     R.need = (int32_t*)(ws + q.need);
     R.lists = (int32_t*)(ws + q.lists);
@@ -614,6 +616,13 @@ gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_ru
       gsgp_destroy(h);
       return fail(GSGP_ERR_NONFINITE, "run %d: X or y holds NaN/Inf (or |y| > FLT_MAX)", i);
     }
+    h->runs_h[i].x_big = h->pinned[kStWords * i + kStXBig];
+  }
+  e = upload_runs(h);
+  if (e != hipSuccess) {
+    gsgp_status s2 = fail(GSGP_ERR_HIP, "gsgp_init: %s", hipGetErrorString(e));
+    gsgp_destroy(h);
+    return s2;
   }
   if (check_guards(h, GSGP_OK) != GSGP_OK) {
     const std::string why = g_last_error;

@@ -63,7 +63,8 @@ def test_spill_stacks_are_sized_for_the_deepest_possible_genome():
     base = gsgp.workspace_size(gsgp.Settings(genome_len=66), runs)
     for k in (67, 127, 2047):
         extra = gsgp.workspace_size(gsgp.Settings(genome_len=k), runs) - base
-        genomes = (128 + 128) * (k - 66) * (4 + 8) * 2
+        # codes and constants, compiled ops and constants, reciprocals
+        genomes = (128 + 128) * (k - 66) * ((4 + 8) * 2 + 8)
         spill = 128 * (k - 3) * 2 * 64 * 8
         assert spill + genomes <= extra <= spill + genomes + 4096, k
     two = gsgp.workspace_size(gsgp.Settings(genome_len=127), runs * 2) - gsgp.workspace_size(
@@ -72,12 +73,12 @@ def test_spill_stacks_are_sized_for_the_deepest_possible_genome():
 
 
 def test_guard_flag_adds_one_guard_per_buffer():
-    """GSGP_FLAG_GUARDS: 4 shared buffers plus 22 per run, each followed by
+    """GSGP_FLAG_GUARDS: 4 shared buffers plus 23 per run, each followed by
     a 256-byte guard (rounded up to the 256-byte buffer alignment)."""
     for runs in ([(500, 200, 8)], [(500, 200, 8), (900, 0, 3)]):
         plain = gsgp.workspace_size(gsgp.Settings(), runs)
         guarded = gsgp.workspace_size(gsgp.Settings(flags=gsgp.FLAG_GUARDS), runs)
-        n_guards = 4 + 22 * len(runs)
+        n_guards = 4 + 23 * len(runs)
         assert plain + 256 * n_guards <= guarded <= plain + 512 * n_guards
 
 

@@ -104,6 +104,75 @@ def test_hand_worked_programs_on_gpu():
     R.close()
 
 
+def _division_data(rng, n, big):
+    """Features at the edges of the interpreter's short division: tiny and
+    subnormal values, values around 1e-6 and 2^-700, values up to FLT_MAX,
+    all-ones significands, signed zeros, small integers; with `big`, also
+    values far beyond 2^128 (the short form is then off for features)."""
+    sign = rng.choice([-1.0, 1.0], size=n)
+    cols = [
+        rng.uniform(-1.0, 1.0, n),
+        sign * 10.0 ** rng.uniform(-322, -290, n),
+        sign * 1e-6 * (1.0 + rng.integers(-2, 3, n) * 2.0 ** -52),
+        sign * 2.0 ** -700 * rng.uniform(0.25, 4.0, n),
+        sign * 10.0 ** rng.uniform(30, 38.53, n),
+        sign * (2.0 - 2.0 ** -52) * 2.0 ** rng.integers(-30, 31, n),
+        sign * 0.0,
+        rng.integers(1, 11, n).astype(np.float64),
+        # inside the short form's limits in every case, up to them
+        sign * 1e-6 * (1.0 + rng.integers(0, 3, n) * 2.0 ** -52),
+        sign * 2.0 ** -700 * rng.uniform(1.0, 4.0, n),
+        sign * 2.0 ** 127 * rng.uniform(0.5, 1.0, n),
+    ]
+    if big:
+        cols.append(sign * 10.0 ** rng.uniform(100, 300, n))
+    return np.stack(cols, axis=1)
+
+
+def _division_genomes(rng, rows, k, l):
+    """Programs made mostly of divisions, with constants at the same edges."""
+    codes = np.empty((rows, k), np.int32)
+    consts = np.zeros((rows, k))
+    edge = np.array([1e-6, -1e-6, 9.999999999999999e-07, 1.0000000000000002e-06, 2.0 ** -700, 2.0 ** 128,
+                     -(2.0 ** 128), 3.4e38, 1e300, 0.0, 2.0 - 2.0 ** -52, 0.5, 3.0, 1e-300])
+    for t in range(rows):
+        for q in range(k):
+            u = rng.random()
+            if u < 0.45:
+                codes[t, q] = -4  # division
+            elif u < 0.6:
+                codes[t, q] = -1 - int(rng.integers(0, 3))
+            elif u < 0.85:
+                codes[t, q] = int(rng.integers(0, l))
+            else:
+                codes[t, q] = -5
+                consts[t, q] = float(rng.choice(edge)) if rng.random() < 0.7 else float(rng.uniform(-1, 1))
+    return codes, consts
+
+
+@pytest.mark.parametrize("big", [False, True])
+def test_division_at_the_short_form_limits_is_bit_exact(big):
+    """FP64 semantics of division-heavy programs on operands at every limit
+    of the short division (divisor 1e-6 and 2^128, dividend 2^-700,
+    quotient 2^127, subnormals, zeros, FLT_MAX overflow): the bits of the
+    oracle's correctly rounded a / b, signed zeros included."""
+    rng = np.random.default_rng(4242 + big)
+    n, m, k = 1300, 512, 40
+    X = _division_data(rng, n, big)
+    l = X.shape[1]
+    d = synth.Dataset(X[:1000], np.zeros(1000), X[1000:], np.zeros(n - 1000))
+    codes, consts = _division_genomes(rng, m + 1, k, l)
+    s = gsgp.Settings(pop_size=m, pool_size=1, genome_len=k, n_generations_max=1, seed=3)
+    R = _runner(s, [d])
+    R.eval_population(codes, consts)
+    got = R.semantics(0, 0)
+    want = orc.interpret(codes[:m], consts[:m], X)
+    assert got.shape == want.shape
+    diff = got.view(np.int64) != want.view(np.int64)
+    assert not diff.any(), (int(diff.sum()), np.argwhere(diff)[:5])
+    R.close()
+
+
 def _deep_genome(rng, D, k, l):
     """D terminals then D - 1 functions: a stack D values deep, right-aligned
     after functions that the interpreter skips (stack too short)."""
@@ -582,9 +651,9 @@ def test_workspace_guards_stay_intact_and_catch_an_overwrite(precision):
     R.time_eval()
     R.generation(5)
     offs = R.guard_offsets()
-    assert offs.size == 4 + 22 * 3
+    assert offs.size == 4 + 23 * 3
     base = R._ws_ptr - R._ws.data_ptr()
-    at = int(base + offs[4 + 22 + 2])  # after S[0] of run 1
+    at = int(base + offs[4 + 23 + 2])  # after S[0] of run 1
     R._ws[at:at + 4] = 0
     R.torch.cuda.synchronize()
     with pytest.raises(gsgp.GSGPError) as e:
