@@ -27,6 +27,15 @@ constexpr int kSegPad = 64;
 constexpr int kWave = 64;
 // Interpreter work unit: a block of kInterpCases cases (kWave lanes x 2 cases).
 constexpr int kInterpCases = 128;
+// X is stored in tiles of kXTile cases, each tile feature-major: element
+// (case c, feature f) at ((c / kXTile) * l + f) * kXTile + c % kXTile.  One
+// tile's features (l x 2 KiB) are contiguous, so the rows an interpreter
+// block reads spread over every L2 channel and few pages, where a
+// feature-major [l][ld] layout put them ld x 8 bytes apart.
+constexpr int kXTile = 256;
+__host__ __device__ constexpr int64_t x_index(int64_t c, int64_t f, int64_t l) {
+  return ((c / kXTile) * l + f) * kXTile + c % kXTile;
+}
 constexpr int kMaxTournament = 64;
 // The interpreter keeps the top two stack values in registers and the rest
 // (depth - 2 values per lane) in a lane-strided column: in LDS up to this
@@ -92,7 +101,7 @@ struct RunDev {
   void* S[2];               // population semantics ping-pong, [m][ld], storage type
   void* sigR;               // squashed pool semantics, [r][ld]
   void* y;                  // target, [ld], storage type, zero pads
-  double* X;                // features, feature-major [l][ld], zero pads
+  double* X;                // features in case tiles, [ceil(ld / kXTile)][l][kXTile], zero pads
   double* part;             // chunk partial sums of squared residuals, [nch][m]; with local
                             // search the generation's sums of o, o^2 and o * t, [nch][3][m]
   double* F[2];             // train RMSE ping-pong, [m]

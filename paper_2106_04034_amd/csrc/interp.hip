@@ -86,8 +86,9 @@ __global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs
     if (c >= 0) {
       prev = (kClsPush << 2) | kPushFeature | dfield | (c << 16);
       ops[n] = prev;
-      // the address of the feature's row in this run's X, bit for bit (see eval_program)
-      opv[n] = __longlong_as_double((long long)(R.X + (int64_t)c * R.ld));
+      // the byte offset of the feature's row in a tile of this run's X, bit
+      // for bit (see eval_program)
+      opv[n] = __longlong_as_double((long long)((int64_t)c * kXTile * (int64_t)sizeof(double)));
       opy[n] = 0.0;
       ++n;
       ++depth;
@@ -207,16 +208,19 @@ __device__ __forceinline__ void eval_program(const int32_t* ops, const double* o
     nos[v] = 0.0;
   }
   // lanes past the last column read the last column instead (no exec-mask
-  // branches around the loads); their values are never stored
+  // branches around the loads); their values are never stored.  BAKED: X is
+  // the handle's own X at the tile that holds the cases, and every lane reads
+  // its own column of the tile (tiles are whole, padding included).
   int64_t at[V];
 #pragma unroll
-  for (int v = 0; v < V; ++v) at[v] = ok[v] ? col[v] : ld - 1;
+  for (int v = 0; v < V; ++v) at[v] = BAKED ? col[v] % kXTile : ok[v] ? col[v] : ld - 1;
   auto feature = [&](int w, double c, double (&x)[V]) {
-    // BAKED: the compile step stored the address of the feature's row in the
-    // handle's own X in the op's constant slot (a pointer's bits, never used
-    // as a number); other callers pass an X of their own and use the index
+    // BAKED: the compile step stored the byte offset of the feature's row in
+    // a tile in the op's constant slot (an integer's bits, never used as a
+    // number); other callers pass a feature-major X of their own and use the
+    // index
     const GSGP_GLOBAL double* xg =
-        BAKED ? (const GSGP_GLOBAL double*)__double_as_longlong(c)
+        BAKED ? (const GSGP_GLOBAL double*)((const char*)X + __double_as_longlong(c))
               : (const GSGP_GLOBAL double*)X + (int64_t)((uint32_t)w >> 16) * ld;
 #pragma unroll
     for (int v = 0; v < V; ++v) x[v] = xg[at[v]];
@@ -350,9 +354,8 @@ __device__ __forceinline__ void eval_program_wide(const int32_t* ops, const doub
   // raw buffer over X: no stride, num_records at the largest offset, and the
   // third descriptor word of a plain dword buffer on gfx9-family parts
   const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, 0x7fffffff, 0x00020000);
-  const uint64_t xbase = (uint64_t)X;
   auto feature = [&](double c, double (&x)[V]) {
-    const int row = (int)((uint64_t)__double_as_longlong(c) - xbase);
+    const int row = (int)__double_as_longlong(c);  // the row's byte offset in the tile
 #pragma unroll
     for (int v = 0; v < V; ++v)
       x[v] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(xr, (int)off[v], row, 0));
@@ -574,7 +577,8 @@ __global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ ru
     if (need <= lo || need > slots) continue;
     double out[kInterpV];
     eval_program<kInterpV, true>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k, uni(cload(&R.nops[prog])),
-                                 R.X, ld, col, ok, (LdsStack)stk, lane, out);
+                                 R.X + (cb * kInterpTile / kXTile) * R.l * kXTile, ld, col, ok, (LdsStack)stk, lane,
+                                 out);
     store_program<T, kInterpV>(R, p, prog, col, ok, out);
   }
 }
@@ -586,13 +590,15 @@ __global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ ru
 // programs with lo < need <= SLOTS.  One wave per block: a block's LDS and
 // slot are released as soon as its one program is done, where four waves
 // of unequal programs held them until the longest ended (3 % faster at the
-// Section 3.1 shape, 7 % on 256 small runs).  Every lane's byte
-// offset into a feature row (its case, or the last column for lanes past
-// it, whose values are never stored) fits in 32 bits, and so does a feature
-// row's offset in X: the runtime uses this kernel only when every run's X
-// is smaller than 2 GiB.
+// Section 3.1 shape, 7 % on 256 small runs).  A block's case block is one
+// tile of X: the feature loads go through a buffer over that tile, with the
+// row's byte offset as the scalar offset and the lane's column as the
+// vector offset (lanes past the last case read the tile's padding and are
+// never stored); a tile is smaller than 2 GiB for any feature count the
+// runtime accepts for this kernel.
 constexpr int kWideV = 4;
 constexpr int kWideTile = kWave * kWideV;
+static_assert(kWideTile == kXTile && kXTile % kInterpTile == 0, "interpreter case blocks lie inside one X tile");
 constexpr int kWideWaves = 1;
 
 template <typename T, int SLOTS>
@@ -618,11 +624,12 @@ __global__ __launch_bounds__(kWideWaves * kWave) void k_interpret_wide(const Run
   for (int v = 0; v < kWideV; ++v) {
     col[v] = cb * kWideTile + v * kWave + lane;
     ok[v] = col[v] < R.ld;
-    off[v] = (uint32_t)((ok[v] ? col[v] : R.ld - 1) * (int64_t)sizeof(double));
+    off[v] = (uint32_t)((v * kWave + lane) * sizeof(double));  // the lane's column of the tile
   }
   double out[kWideV];
   eval_program_wide<kWideV>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k, R.opy + (int64_t)prog * p.k,
-                            R.X, uni(R.x_big) == 0, off, (LdsStack)(lds + wave * SLOTS * kWideV * kWave), lane, out);
+                            R.X + cb * R.l * kXTile, uni(R.x_big) == 0, off,
+                            (LdsStack)(lds + wave * SLOTS * kWideV * kWave), lane, out);
   store_program<T, kWideV>(R, p, prog, col, ok, out);
 }
 
@@ -658,7 +665,8 @@ __global__ __launch_bounds__(64) void k_interpret_spill(const RunDev* __restrict
       }
       double out[kInterpV];
       eval_program<kInterpV, true>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k,
-                                   uni(cload(&R.nops[prog])), R.X, R.ld, col, ok, (GlobalStack)stk, lane, out);
+                                   uni(cload(&R.nops[prog])), R.X + (cb * kInterpTile / kXTile) * R.l * kXTile, R.ld,
+                                   col, ok, (GlobalStack)stk, lane, out);
       store_program<T, kInterpV>(R, p, prog, col, ok, out);
     }
   }

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) void k_prep(const RunDev* __restrict__ runs, P
     const double v = (row >= 0) ? Xs[row * R.l + f] : 0.0;
     bad |= !isfinite(v);
     big |= fabs(v) > 0x1p128;
-    R.X[(int64_t)f * R.ld + col] = v;
+    R.X[x_index(col, f, R.l)] = v;
   }
   const double yv = (row >= 0) ? ys[row] : 0.0;
   bad |= !isfinite(yv) || fabs(yv) > kFltMax;

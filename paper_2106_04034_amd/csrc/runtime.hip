@@ -180,7 +180,7 @@ gsgp_status make_plan(const gsgp_config* c, const gsgp_run* runs, int32_t n_runs
     const int64_t chunk = chunk_cases((int)s);
     p.nch_tr = (int32_t)((p.tr_pad + chunk - 1) / chunk);
     p.nch_te = (int32_t)((p.te_pad + chunk - 1) / chunk);
-    p.X = take_at(sizeof(double) * p.l * p.ld, i, "X");
+    p.X = take_at(sizeof(double) * p.l * ((p.ld + kXTile - 1) / kXTile) * kXTile, i, "X");
     p.y = take_at(s * p.ld, i, "y");
     p.S0 = take_at(s * m * p.ld, i, "S[0]");
     p.S1 = take_at(s * m * p.ld, i, "S[1]");
@@ -226,7 +226,7 @@ struct gsgp_handle {
   VaryLaunch vary{}, rows{};
   int64_t interp_tasks = 0;  // interpreter case blocks over all runs
   int64_t interp_tasks_w = 0;  // wide interpreter case blocks over all runs
-  bool interp_wide = false;    // every run's X is smaller than 2 GiB
+  bool interp_wide = false;    // an X tile of every run is smaller than 2 GiB
   int32_t surv_blocks = 0;
   int32_t slots = 1;         // interpreter stack values per lane in LDS
   int32_t max_blocks = 0;
@@ -569,7 +569,7 @@ gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_ru
     itask += (q.ld + kInterpCases - 1) / kInterpCases;
     R.cblk0w = itask_w;
     itask_w += (q.ld + 4 * kWave - 1) / (4 * kWave);
-    wide_ok = wide_ok && (uint64_t)q.ld * q.l * sizeof(double) < ((uint64_t)1 << 31);
+    wide_ok = wide_ok && (uint64_t)q.l * kXTile * sizeof(double) < ((uint64_t)1 << 31);
     R.surv_blk0 = sblk;
     // survival blocks per run: each copies about 16 KiB of an elite row
     const int64_t nb = ((int64_t)storage_bytes(cfg->precision) * q.ld + 16383) / 16384;
@@ -602,6 +602,12 @@ gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_ru
     e = hipMemcpyAsync((void*)d_src, src.data(), sizeof(double*) * src.size(), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(state, zeros.data(), sizeof(int32_t) * zeros.size(), hipMemcpyHostToDevice, h->stream);
+  // X's last tile of each run is whole: its columns past the padded cases
+  // are read by interpreter lanes whose values are never stored; zeros
+  for (int32_t i = 0; i < n_runs && e == hipSuccess; ++i) {
+    const RunPlan& q = plan.runs[i];
+    e = hipMemsetAsync(ws + q.X, 0, sizeof(double) * q.l * ((q.ld + kXTile - 1) / kXTile) * kXTile, h->stream);
+  }
   if (e == hipSuccess) e = launch_prep(h->runs_d, p, col, d_src, nullptr, h->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(h->pinned, state, sizeof(int32_t) * kStWords * n_runs, hipMemcpyDeviceToHost, h->stream);
