@@ -591,56 +591,56 @@ __global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ ru
   }
 }
 
-// ComputeSemantics with eval_program_wide: a block of kWideWaves waves takes
-// one block of kWideTile cases of one run (lanes own kWideV cases each) and
-// kWideWaves programs of one stack-need list, one per wave; a wave's LDS
-// column holds SLOTS stack values per lane.  The pass takes the list's
-// programs with lo < need <= SLOTS.  One wave per block: a block's LDS and
-// slot are released as soon as its one program is done, where four waves
-// of unequal programs held them until the longest ended (3 % faster at the
-// Section 3.1 shape, 7 % on 256 small runs).  A block's case block is one
-// tile of X: the feature loads go through a buffer over that tile, with the
-// row's byte offset as the scalar offset and the lane's column as the
-// vector offset (lanes past the last case read the tile's padding and are
-// never stored); a tile is smaller than 2 GiB for any feature count the
-// runtime accepts for this kernel.
-constexpr int kWideV = 4;
-constexpr int kWideTile = kWave * kWideV;
-static_assert(kWideTile == kXTile && kXTile % kInterpTile == 0, "interpreter case blocks lie inside one X tile");
-constexpr int kWideWaves = 1;
+// ComputeSemantics with eval_program_wide: a block of one wave takes one
+// block of 64 x V cases of one run (each lane owns V of them) and one
+// program of a stack-need list; the wave's LDS column holds SLOTS stack
+// values per lane.  The pass takes the list's programs with lo < need <=
+// SLOTS.  One wave per block: a block's LDS and slot are released as soon
+// as its program is done, where four waves of unequal programs held them
+// until the longest ended (3 % faster at the Section 3.1 shape, 7 % on 256
+// small runs).  V = 4 (256 cases) for the shallow lists, V = 2 (128 cases)
+// for the deepest, whose LDS column bounds the resident waves (each stack
+// value costs V x 512 bytes of LDS per wave).  A block's cases lie in one
+// tile of X: the
+// feature loads go through a buffer over that tile, with the row's byte
+// offset as the scalar offset and the lane's column as the vector offset
+// (lanes past the last case read the tile's padding and are never stored);
+// a tile is smaller than 2 GiB for any feature count the runtime accepts
+// for this kernel.
+static_assert(kXTile == 4 * kWave && kXTile % kInterpTile == 0, "interpreter case blocks lie inside one X tile");
 
-template <typename T, int SLOTS>
-__global__ __launch_bounds__(kWideWaves * kWave) void k_interpret_wide(const RunDev* __restrict__ runs, Params p,
-                                                                        int32_t pgroups, int lo, int list) {
-  __shared__ double lds[kWideWaves * SLOTS * kWideV * kWave];
+template <typename T, int SLOTS, int V>
+__global__ __launch_bounds__(kWave) void k_interpret_wide(const RunDev* __restrict__ runs, Params p, int32_t pgroups,
+                                                          int lo, int list) {
+  static_assert(V == 2 || V == 4, "two or four cases per lane");
+  constexpr int kTile = kWave * V;
+  __shared__ double lds[SLOTS * V * kWave];
   const int lane = threadIdx.x & 63;
-  const int wave = uni(threadIdx.x >> 6);
   const int64_t cbg = blockIdx.x / pgroups;  // case block over all runs
   const int pg = (int)(blockIdx.x - cbg * pgroups);
-  const int run = find_run(p.n_runs, cbg, [&](int r) { return runs[r].cblk0w; });
+  const int run = find_run(p.n_runs, cbg, [&](int r) { return V == 4 ? runs[r].cblk0w : runs[r].cblk0; });
   const RunDev& R = runs[run];
-  const int64_t cb = cbg - R.cblk0w;
-  const int idx = pg * kWideWaves + wave;
-  if (idx >= uni(cload(&R.state[kStList0 + list]))) return;
-  const int prog = uni(cload(&R.lists[(int64_t)list * (p.m + p.r) + idx]));
+  const int64_t cb = cbg - (V == 4 ? R.cblk0w : R.cblk0);
+  if (pg >= uni(cload(&R.state[kStList0 + list]))) return;
+  const int prog = uni(cload(&R.lists[(int64_t)list * (p.m + p.r) + pg]));
   const int need = uni(cload(&R.need[prog]));
   if (need <= lo || need > SLOTS) return;
-  int64_t col[kWideV];
-  bool ok[kWideV];
-  uint32_t off[kWideV];
+  const int64_t first = cb * kTile;  // the block's first case
+  int64_t col[V];
+  bool ok[V];
+  uint32_t off[V];
 #pragma unroll
-  for (int v = 0; v < kWideV; ++v) {
-    // lane l owns cases 2l, 2l + 1, 128 + 2l and 129 + 2l of the tile
+  for (int v = 0; v < V; ++v) {
+    // lane l owns cases 2l and 2l + 1 (and 128 + 2l, 129 + 2l) of the block
     const int c = (v >> 1) * (2 * kWave) + 2 * lane + (v & 1);
-    col[v] = cb * kWideTile + c;
+    col[v] = first + c;
     ok[v] = col[v] < R.ld;
-    off[v] = (uint32_t)(c * sizeof(double));  // the lane's column of the tile
+    off[v] = (uint32_t)((first % kXTile + c) * sizeof(double));  // the lane's column of the tile
   }
-  double out[kWideV];
-  eval_program_wide<kWideV>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k, R.opy + (int64_t)prog * p.k,
-                            R.X + cb * R.l * kXTile, uni(R.x_big) == 0, off,
-                            (LdsStack)(lds + wave * SLOTS * kWideV * kWave), lane, out);
-  store_program<T, kWideV>(R, p, prog, col, ok, out);
+  double out[V];
+  eval_program_wide<V>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k, R.opy + (int64_t)prog * p.k,
+                       R.X + (first / kXTile) * R.l * kXTile, uni(R.x_big) == 0, off, (LdsStack)lds, lane, out);
+  store_program<T, V>(R, p, prog, col, ok, out);
 }
 
 // Last pass: the programs of the last list whose stack exceeds the largest
@@ -790,35 +790,42 @@ hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_
   return hipGetLastError();
 }
 
-template <typename T, int SLOTS>
-void launch_wide_as(const RunDev* d_runs, const Params& p, dim3 grid, int32_t pgroups, int lo, int list,
-                    hipStream_t s) {
-  hipLaunchKernelGGL((k_interpret_wide<T, SLOTS>), grid, dim3(kWideWaves * kWave), 0, s, d_runs, p, pgroups, lo,
+// Cases per lane of each list's pass (see k_interpret_wide).
+// Four cases per lane except for the deepest list, whose 6-value column
+// would hold the LDS to 13 waves per CU (V = 2 there: 4 % faster at the
+// Section 3.1 shape with 2,047 genes; two cases per lane on the other lists
+// was slower).
+constexpr int kListV[kLists - 1] = {4, 4, 4, 2};
+
+template <typename T, int B>
+void launch_wide_list(const RunDev* d_runs, const Params& p, int64_t case_blocks, int32_t progs, int lo, int list,
+                      hipStream_t s) {
+  const dim3 grid((unsigned)(case_blocks * progs));
+  hipLaunchKernelGGL((k_interpret_wide<T, kListSlots[B], kListV[B]>), grid, dim3(kWave), 0, s, d_runs, p, progs, lo,
                      list);
 }
 
 template <typename T>
-hipError_t launch_wide_slots(const RunDev* d_runs, const Params& p, dim3 grid, int32_t pgroups, int lo, int slots,
-                             int list, hipStream_t s) {
-  switch (slots) {
-    case kListSlots[0]: launch_wide_as<T, kListSlots[0]>(d_runs, p, grid, pgroups, lo, list, s); break;
-    case kListSlots[1]: launch_wide_as<T, kListSlots[1]>(d_runs, p, grid, pgroups, lo, list, s); break;
-    case kListSlots[2]: launch_wide_as<T, kListSlots[2]>(d_runs, p, grid, pgroups, lo, list, s); break;
-    case kListSlots[3]: launch_wide_as<T, kListSlots[3]>(d_runs, p, grid, pgroups, lo, list, s); break;
+hipError_t launch_wide_lists(const RunDev* d_runs, const Params& p, int64_t blocks256, int64_t blocks128, int lo,
+                             int list, int32_t progs, hipStream_t s) {
+  const int64_t case_blocks = kListV[list] == 4 ? blocks256 : blocks128;
+  if (case_blocks * progs > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  switch (list) {
+    case 0: launch_wide_list<T, 0>(d_runs, p, case_blocks, progs, lo, list, s); break;
+    case 1: launch_wide_list<T, 1>(d_runs, p, case_blocks, progs, lo, list, s); break;
+    case 2: launch_wide_list<T, 2>(d_runs, p, case_blocks, progs, lo, list, s); break;
+    case 3: launch_wide_list<T, 3>(d_runs, p, case_blocks, progs, lo, list, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_interpret_wide(const RunDev* d_runs, const Params& p, int64_t case_blocks, int lo, int slots,
+hipError_t launch_interpret_wide(const RunDev* d_runs, const Params& p, int64_t blocks256, int64_t blocks128, int lo,
                                  int list, int32_t progs, hipStream_t s) {
-  if (list < 0 || list >= kLists) return hipErrorInvalidValue;
+  if (list < 0 || list >= kLists - 1) return hipErrorInvalidValue;
   if (progs <= 0) return hipSuccess;
-  const int32_t pgroups = (progs + kWideWaves - 1) / kWideWaves;
-  if (case_blocks * pgroups > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  const dim3 grid((unsigned)(case_blocks * pgroups));
-  return p.precision == GSGP_FP64 ? launch_wide_slots<double>(d_runs, p, grid, pgroups, lo, slots, list, s)
-                                  : launch_wide_slots<float>(d_runs, p, grid, pgroups, lo, slots, list, s);
+  return p.precision == GSGP_FP64 ? launch_wide_lists<double>(d_runs, p, blocks256, blocks128, lo, list, progs, s)
+                                  : launch_wide_lists<float>(d_runs, p, blocks256, blocks128, lo, list, progs, s);
 }
 
 hipError_t launch_interpret_spill(const RunDev* d_runs, const Params& p, double* spill, int slots,

@@ -653,8 +653,8 @@ namespace {
 // ComputeSemantics of every compiled program, in one pass per stack-need
 // list, each with the smallest LDS column that holds its programs (more
 // resident waves for the shallow lists): the first kLists - 1 lists with the
-// four-cases-per-lane kernel (handles whose runs each have an X smaller
-// than 2 GiB, all practical ones) or else the two-cases-per-lane kernel,
+// wide kernel (handles whose runs each have an X tile smaller than 2 GiB,
+// all practical ones) or else the two-cases-per-lane kernel,
 // then the last list with columns up to kMaxLdsSlots, then the programs
 // beyond any LDS column (spill stacks).  counts[b]: the longest list b over
 // the runs.
@@ -664,7 +664,7 @@ hipError_t interpret_all(gsgp_handle* h, const int32_t (&counts)[kLists], hipStr
   for (int b = 0; b < kLists - 1 && e == hipSuccess; ++b) {
     const int lo = b == 0 ? -1 : kListSlots[b - 1];
     if (h->interp_wide)
-      e = launch_interpret_wide(h->runs_d, p, h->interp_tasks_w, lo, kListSlots[b], b, counts[b], s);
+      e = launch_interpret_wide(h->runs_d, p, h->interp_tasks_w, h->interp_tasks, lo, b, counts[b], s);
     else
       e = launch_interpret(h->runs_d, p, h->interp_tasks, lo, kListSlots[b], b, counts[b], s);
   }
