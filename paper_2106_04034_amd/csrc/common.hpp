@@ -208,8 +208,7 @@ hipError_t launch_compile(const RunDev* d_runs, const Params& p, hipStream_t s);
 // cases per lane, any slots up to kMaxLdsSlots, case_blocks blocks of
 // kInterpCases cases; launch_interpret_wide: list < kLists - 1 with its
 // LDS column of kListSlots[list] values, two or four cases per lane (blocks
-// of kInterpCases or kXTile cases over all runs: blocks128, blocks256), for
-// handles whose runs each have an X tile smaller than 2 GiB.
+// of kInterpCases or kXTile cases over all runs: blocks128, blocks256).
 hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_blocks, int lo, int slots,
                             int list, int32_t progs, hipStream_t s);
 hipError_t launch_interpret_wide(const RunDev* d_runs, const Params& p, int64_t blocks256, int64_t blocks128, int lo,

@@ -5,13 +5,15 @@
 //                     interpreter would skip and the pushes after the last
 //                     function, fuses each push with a function that
 //                     directly consumes it, and records every op's stack
-//                     depth;
-//   k_interpret_wide  one wavefront per (program, 256 cases), four cases per
-//                     lane: the compiled program is wave-uniform (no
-//                     divergence), the top two stack values live in
-//                     registers and the rest in a lane-strided LDS column;
-//   k_interpret       the same with two cases per lane and LDS columns up to
-//                     63 values (deeper programs); k_interpret_spill beyond;
+//                     depth; k_order files the programs into lists by stack
+//                     need, longest first;
+//   k_interpret_wide  one wavefront per (program, 256 or 128 cases), four
+//                     or two cases per lane: the compiled program is
+//                     wave-uniform (no divergence), the top two stack values
+//                     live in registers and the rest in a lane-strided LDS
+//                     column sized for the list;
+//   k_interpret       the same evaluator with LDS columns up to 63 values
+//                     (deeper programs); k_interpret_spill beyond;
 //   k_interpret_list  given programs on new cases (lineage reconstruction).
 // This translation unit is built with
 // -structurizecfg-skip-uniform-regions: the interpreter dispatches every op
@@ -189,12 +191,13 @@ __global__ __launch_bounds__(1024) void k_order(const RunDev* __restrict__ runs,
 // push the next function consumes) applies the function to tos and the
 // terminal and touches neither nos nor LDS.  The value of the program is the
 // output of its last function (the Out register), 0.0 if none runs.
-// X is feature-major in global memory, row stride ld; one case block's
-// features stay in L2 while the block's programs run.
+// This form serves the list interpreter (programs on a caller's cases): X is
+// feature-major in global memory, row stride ld, and a feature op's index
+// sits in its op word.
 typedef GSGP_LDS double* LdsStack;        // stack column in LDS
 typedef GSGP_GLOBAL double* GlobalStack;  // stack column in the workspace (spill pass)
 
-template <int V, bool BAKED, typename Stack>
+template <int V, typename Stack>
 __device__ __forceinline__ void eval_program(const int32_t* ops, const double* opv, int n, const double* X,
                                              int64_t ld, const int64_t (&col)[V], const bool (&ok)[V],
                                              Stack stk, int lane, double (&out)[V]) {
@@ -208,20 +211,12 @@ __device__ __forceinline__ void eval_program(const int32_t* ops, const double* o
     nos[v] = 0.0;
   }
   // lanes past the last column read the last column instead (no exec-mask
-  // branches around the loads); their values are never stored.  BAKED: X is
-  // the handle's own X at the tile that holds the cases, and every lane reads
-  // its own column of the tile (tiles are whole, padding included).
+  // branches around the loads); their values are never stored
   int64_t at[V];
 #pragma unroll
-  for (int v = 0; v < V; ++v) at[v] = BAKED ? col[v] % kXTile : ok[v] ? col[v] : ld - 1;
-  auto feature = [&](int w, double c, double (&x)[V]) {
-    // BAKED: the compile step stored the byte offset of the feature's row in
-    // a tile in the op's constant slot (an integer's bits, never used as a
-    // number); other callers pass a feature-major X of their own and use the
-    // index
-    const GSGP_GLOBAL double* xg =
-        BAKED ? (const GSGP_GLOBAL double*)((const char*)X + __double_as_longlong(c))
-              : (const GSGP_GLOBAL double*)X + (int64_t)((uint32_t)w >> 16) * ld;
+  for (int v = 0; v < V; ++v) at[v] = ok[v] ? col[v] : ld - 1;
+  auto feature = [&](int w, double (&x)[V]) {
+    const GSGP_GLOBAL double* xg = (const GSGP_GLOBAL double*)X + (int64_t)((uint32_t)w >> 16) * ld;
 #pragma unroll
     for (int v = 0; v < V; ++v) x[v] = xg[at[v]];
   };
@@ -251,7 +246,7 @@ __device__ __forceinline__ void eval_program(const int32_t* ops, const double* o
 #pragma unroll
         for (int v = 0; v < V; ++v) nos[v] = tos[v];
         if (fn == kPushFeature) {
-          feature(w, cv[u], tos);
+          feature(w, tos);
         } else {
 #pragma unroll
           for (int v = 0; v < V; ++v) tos[v] = cv[u];
@@ -299,7 +294,7 @@ __device__ __forceinline__ void eval_program(const int32_t* ops, const double* o
 #pragma unroll
           for (int v = 0; v < V; ++v) t0[v] = tos[v];
           if (cls == kClsFeature) {
-            feature(w, cv[u], x);
+            feature(w, x);
           } else {
 #pragma unroll
             for (int v = 0; v < V; ++v) x[v] = cv[u];
@@ -522,6 +517,22 @@ static_assert(kInterpTile == kInterpCases, "the runtime plans kInterpCases-case 
 // count as a launch argument instead of a constant cost 3 %.
 constexpr int kInterpProgsPerWave = 1;
 
+// The cases of a lane in a block of 64 x V cases starting at case `first`
+// (a multiple of 64 x V inside one X tile): lane l owns cases 2l and 2l + 1
+// (and, for V = 4, 128 + 2l and 129 + 2l), so that each pair is one 16-byte
+// load; off[v] is the case's byte offset in its row of the X tile.
+template <int V>
+__device__ __forceinline__ void lane_cases(int64_t first, int lane, int64_t ld, int64_t (&col)[V], bool (&ok)[V],
+                                           uint32_t (&off)[V]) {
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const int c = (v >> 1) * (2 * kWave) + 2 * lane + (v & 1);
+    col[v] = first + c;
+    ok[v] = col[v] < ld;
+    off[v] = (uint32_t)((first % kXTile + c) * sizeof(double));
+  }
+}
+
 // Writes one program's values for one case block: population rows as they
 // are, pool rows squashed by the logistic function (the random functions R_u
 // of GSM, Section 2); padding columns as exact zeros.
@@ -565,16 +576,13 @@ __global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ ru
   const int run = find_run(p.n_runs, cbg, [&](int r) { return runs[r].cblk0; });
   const RunDev& R = runs[run];
   const int64_t cb = cbg - R.cblk0;
-  const int64_t ld = R.ld;
   const int rows = p.m + p.r;
   double* stk = lds + wave * slots * kInterpV * kWave;
+  const int64_t first = cb * kInterpTile;
   int64_t col[kInterpV];
   bool ok[kInterpV];
-#pragma unroll
-  for (int v = 0; v < kInterpV; ++v) {
-    col[v] = cb * kInterpTile + v * kWave + lane;
-    ok[v] = col[v] < ld;
-  }
+  uint32_t off[kInterpV];
+  lane_cases<kInterpV>(first, lane, R.ld, col, ok, off);
   for (int j = 0; j < kInterpProgsPerWave; ++j) {
     const int idx = (pg * kInterpProgsPerWave + j) * W + wave;
     if (idx >= uni(cload(&R.state[kStList0 + list]))) break;
@@ -584,9 +592,9 @@ __global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ ru
     const int need = uni(cload(&R.need[prog]));
     if (need <= lo || need > slots) continue;
     double out[kInterpV];
-    eval_program<kInterpV, true>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k, uni(cload(&R.nops[prog])),
-                                 R.X + (cb * kInterpTile / kXTile) * R.l * kXTile, ld, col, ok, (LdsStack)stk, lane,
-                                 out);
+    eval_program_wide<kInterpV>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k,
+                                R.opy + (int64_t)prog * p.k, R.X + (first / kXTile) * R.l * kXTile,
+                                uni(R.x_big) == 0, off, (LdsStack)stk, lane, out);
     store_program<T, kInterpV>(R, p, prog, col, ok, out);
   }
 }
@@ -604,10 +612,10 @@ __global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ ru
 // tile of X: the
 // feature loads go through a buffer over that tile, with the row's byte
 // offset as the scalar offset and the lane's column as the vector offset
-// (lanes past the last case read the tile's padding and are never stored);
-// a tile is smaller than 2 GiB for any feature count the runtime accepts
-// for this kernel.
+// (lanes past the last case read the tile's padding and are never stored).
 static_assert(kXTile == 4 * kWave && kXTile % kInterpTile == 0, "interpreter case blocks lie inside one X tile");
+static_assert(65535LL * kXTile * sizeof(double) < (1LL << 31), "a tile of the most features the runtime accepts "
+                                                                  "takes 32-bit buffer offsets");
 
 template <typename T, int SLOTS, int V>
 __global__ __launch_bounds__(kWave) void k_interpret_wide(const RunDev* __restrict__ runs, Params p, int32_t pgroups,
@@ -629,14 +637,7 @@ __global__ __launch_bounds__(kWave) void k_interpret_wide(const RunDev* __restri
   int64_t col[V];
   bool ok[V];
   uint32_t off[V];
-#pragma unroll
-  for (int v = 0; v < V; ++v) {
-    // lane l owns cases 2l and 2l + 1 (and 128 + 2l, 129 + 2l) of the block
-    const int c = (v >> 1) * (2 * kWave) + 2 * lane + (v & 1);
-    col[v] = first + c;
-    ok[v] = col[v] < R.ld;
-    off[v] = (uint32_t)((first % kXTile + c) * sizeof(double));  // the lane's column of the tile
-  }
+  lane_cases<V>(first, lane, R.ld, col, ok, off);
   double out[V];
   eval_program_wide<V>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k, R.opy + (int64_t)prog * p.k,
                        R.X + (first / kXTile) * R.l * kXTile, uni(R.x_big) == 0, off, (LdsStack)lds, lane, out);
@@ -666,17 +667,15 @@ __global__ __launch_bounds__(64) void k_interpret_spill(const RunDev* __restrict
       const int prog = uni(cload(&list[j]));
       const int need = uni(cload(&R.need[prog]));
       if (need <= kMaxLdsSlots || need > slots) continue;  // LDS passes took it; never beyond the column
+      const int64_t first = cb * kInterpTile;
       int64_t col[kInterpV];
       bool ok[kInterpV];
-#pragma unroll
-      for (int v = 0; v < kInterpV; ++v) {
-        col[v] = cb * kInterpTile + v * kWave + lane;
-        ok[v] = col[v] < R.ld;
-      }
+      uint32_t off[kInterpV];
+      lane_cases<kInterpV>(first, lane, R.ld, col, ok, off);
       double out[kInterpV];
-      eval_program<kInterpV, true>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k,
-                                   uni(cload(&R.nops[prog])), R.X + (cb * kInterpTile / kXTile) * R.l * kXTile, R.ld,
-                                   col, ok, (GlobalStack)stk, lane, out);
+      eval_program_wide<kInterpV>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k,
+                                  R.opy + (int64_t)prog * p.k, R.X + (first / kXTile) * R.l * kXTile,
+                                  uni(R.x_big) == 0, off, (GlobalStack)stk, lane, out);
       store_program<T, kInterpV>(R, p, prog, col, ok, out);
     }
   }
@@ -702,7 +701,7 @@ __device__ __forceinline__ void list_task(const int32_t* ops, const double* opv,
     ok[v] = col[v] < ld;
   }
   double val[kInterpV];
-  eval_program<kInterpV, false>(ops + (int64_t)pr * k, opv + (int64_t)pr * k, uni(nops[pr]), Xfm, ld, col, ok, stk,
+  eval_program<kInterpV>(ops + (int64_t)pr * k, opv + (int64_t)pr * k, uni(nops[pr]), Xfm, ld, col, ok, stk,
                                 lane, val);
   const bool sq = squash[j] != 0;
 #pragma unroll

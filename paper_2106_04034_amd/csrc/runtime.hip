@@ -226,7 +226,6 @@ struct gsgp_handle {
   VaryLaunch vary{}, rows{};
   int64_t interp_tasks = 0;  // interpreter case blocks over all runs
   int64_t interp_tasks_w = 0;  // wide interpreter case blocks over all runs
-  bool interp_wide = false;    // an X tile of every run is smaller than 2 GiB
   int32_t surv_blocks = 0;
   int32_t slots = 1;         // interpreter stack values per lane in LDS
   int32_t max_blocks = 0;
@@ -523,7 +522,6 @@ gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_ru
   int32_t* state = (int32_t*)(ws + plan.state);
   h->runs_h.resize(n_runs);
   int64_t col = 0, itask = 0, itask_w = 0;
-  bool wide_ok = true;
   int32_t sblk = 0;
   for (int32_t i = 0; i < n_runs; ++i) {
     const RunPlan& q = plan.runs[i];
@@ -569,7 +567,6 @@ gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_ru
     itask += (q.ld + kInterpCases - 1) / kInterpCases;
     R.cblk0w = itask_w;
     itask_w += (q.ld + 4 * kWave - 1) / (4 * kWave);
-    wide_ok = wide_ok && (uint64_t)q.l * kXTile * sizeof(double) < ((uint64_t)1 << 31);
     R.surv_blk0 = sblk;
     // survival blocks per run: each copies about 16 KiB of an elite row
     const int64_t nb = ((int64_t)storage_bytes(cfg->precision) * q.ld + 16383) / 16384;
@@ -578,7 +575,6 @@ gsgp_status gsgp_init(const gsgp_config* cfg, const gsgp_run* runs, int32_t n_ru
   }
   h->interp_tasks = itask;
   h->interp_tasks_w = itask_w;
-  h->interp_wide = wide_ok;
   h->surv_blocks = sblk;
   plan_vary(h, 4, 16, 1, 0);
   plan_rows(h);
@@ -653,20 +649,15 @@ namespace {
 // ComputeSemantics of every compiled program, in one pass per stack-need
 // list, each with the smallest LDS column that holds its programs (more
 // resident waves for the shallow lists): the first kLists - 1 lists with the
-// wide kernel (handles whose runs each have an X tile smaller than 2 GiB,
-// all practical ones) or else the two-cases-per-lane kernel,
-// then the last list with columns up to kMaxLdsSlots, then the programs
-// beyond any LDS column (spill stacks).  counts[b]: the longest list b over
-// the runs.
+// wide kernel, then the last list with columns up to kMaxLdsSlots, then the
+// programs beyond any LDS column (spill stacks).  counts[b]: the longest
+// list b over the runs.
 hipError_t interpret_all(gsgp_handle* h, const int32_t (&counts)[kLists], hipStream_t s) {
   const Params& p = h->params;
   hipError_t e = hipSuccess;
   for (int b = 0; b < kLists - 1 && e == hipSuccess; ++b) {
     const int lo = b == 0 ? -1 : kListSlots[b - 1];
-    if (h->interp_wide)
-      e = launch_interpret_wide(h->runs_d, p, h->interp_tasks_w, h->interp_tasks, lo, b, counts[b], s);
-    else
-      e = launch_interpret(h->runs_d, p, h->interp_tasks, lo, kListSlots[b], b, counts[b], s);
+    e = launch_interpret_wide(h->runs_d, p, h->interp_tasks_w, h->interp_tasks, lo, b, counts[b], s);
   }
   if (e == hipSuccess && h->slots > kListSlots[kLists - 2])
     e = launch_interpret(h->runs_d, p, h->interp_tasks, kListSlots[kLists - 2], std::min(h->slots, kMaxLdsSlots),
