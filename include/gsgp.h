@@ -151,7 +151,7 @@ gsgp_status gsgp_workspace_size(const gsgp_config* cfg, const gsgp_run* runs, in
 
 /* Algorithm 1 set-up (Section 2.1 stages 1-2: work ranges and memory).
  * Validates cfg and runs, carves d_workspace (device, >= gsgp_workspace_size
- * bytes, 256-byte aligned), copies X into a feature-major padded layout and y
+ * bytes, 256-byte aligned), copies X into padded case tiles and y
  * into the storage precision, checks that X and y are finite, and synchronises
  * the stream.  hip_stream is a hipStream_t (NULL = default stream).
  * Errors: GSGP_ERR_ARG, GSGP_ERR_WORKSPACE (too small / misaligned),

@@ -207,8 +207,8 @@ def _stack_depths(codes):
 
 
 def test_deep_programs_take_the_second_interpreter_pass():
-    """Programs whose stack needs more LDS values per lane than the first
-    interpreter pass provides run in a second pass.  A population mixing
+    """Programs whose stack needs more LDS values per lane than the shallow
+    interpreter passes provide run in the deep-list pass.  A population mixing
     random genomes with stacks 8 to 60 values deep, in a handle with a
     second run that has (almost) no deep program, matches the oracle bit for
     bit."""
@@ -860,7 +860,7 @@ def test_philox_population_of_deep_programs_is_accepted():
                       p_function=0.3, p_feature=0.6)
     codes, _ = orc.genomes(oracle_config(s), 3, orc.TAG_POPULATION, 24)
     depth = _stack_depths(codes)
-    assert depth.max() > 65 and (depth <= 7).sum() < len(depth)  # some beyond LDS, most beyond the first pass
+    assert depth.max() > 65 and (depth <= 7).sum() < len(depth)  # some beyond LDS, most beyond the stack-need lists
     _free_run_parity(s, d, 3)
 
 
