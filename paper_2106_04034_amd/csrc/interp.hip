@@ -517,6 +517,15 @@ static_assert(kInterpTile == kInterpCases, "the runtime plans kInterpCases-case 
 // count as a launch argument instead of a constant cost 3 %.
 constexpr int kInterpProgsPerWave = 1;
 
+// Hardware dispatch sends block b of a grid of n to XCD b % 8.  Interpreter
+// blocks are numbered case block by case block; xcd_block gives each XCD a
+// contiguous range of them, so the CUs of one XCD work on the same X tile
+// and each tile is read into one XCD's L2, not into all eight.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t n) {
+  const int64_t x = b & 7, i = b >> 3, q = n >> 3, rem = n & 7;
+  return x * q + (x < rem ? x : rem) + i;
+}
+
 // The cases of a lane in a block of 64 x V cases starting at case `first`
 // (a multiple of 64 x V inside one X tile): lane l owns cases 2l and 2l + 1
 // (and, for V = 4, 128 + 2l and 129 + 2l), so that each pair is one 16-byte
@@ -571,8 +580,9 @@ __global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ ru
   const int lane = threadIdx.x & 63;
   const int wave = uni(threadIdx.x >> 6);
   const int W = blockDim.x >> 6;
-  const int64_t cbg = blockIdx.x / pgroups;  // case block over all runs
-  const int pg = (int)(blockIdx.x - cbg * pgroups);
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t cbg = blk / pgroups;  // case block over all runs
+  const int pg = (int)(blk - cbg * pgroups);
   const int run = find_run(p.n_runs, cbg, [&](int r) { return runs[r].cblk0; });
   const RunDev& R = runs[run];
   const int64_t cb = cbg - R.cblk0;
@@ -624,8 +634,9 @@ __global__ __launch_bounds__(kWave) void k_interpret_wide(const RunDev* __restri
   constexpr int kTile = kWave * V;
   __shared__ double lds[SLOTS * V * kWave];
   const int lane = threadIdx.x & 63;
-  const int64_t cbg = blockIdx.x / pgroups;  // case block over all runs
-  const int pg = (int)(blockIdx.x - cbg * pgroups);
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t cbg = blk / pgroups;  // case block over all runs
+  const int pg = (int)(blk - cbg * pgroups);
   const int run = find_run(p.n_runs, cbg, [&](int r) { return V == 4 ? runs[r].cblk0w : runs[r].cblk0; });
   const RunDev& R = runs[run];
   const int64_t cb = cbg - (V == 4 ? R.cblk0w : R.cblk0);
