@@ -312,39 +312,41 @@ __device__ __forceinline__ void eval_program(const int32_t* ops, const double* o
   for (int v = 0; v < V; ++v) out[v] = tos[v];
 }
 
-// The first interpreter passes: eval_program for V cases per lane with the
-// stack's LDS column bounded at compile time, written to keep the scalar
-// work per op small (the kernel is bound by the scalar unit's issue rate:
-// every op is decoded and dispatched by wave-uniform branches).
+// The interpreter passes over the handle's X: eval_program for V cases per
+// lane, written to keep the work per op small.
 //   - Dispatch tests single bits of the op word: bit 3 a function applied
 //     to the top of the stack and a terminal (fused op), else bit 2 a
 //     function of the top two values, else a push; bit 1 multiplication or
 //     division, bit 0 subtraction or division (or, for a push, a constant).
-//   - A feature op's constant slot holds the absolute address of its row of
-//     the run's X.  Features are read through a buffer resource over the
-//     run's X (smaller than 2 GiB): the scalar offset is the row's byte
-//     offset (one scalar subtraction) and each lane's fixed 32-bit byte
-//     offset (its case) is the vector offset, so a feature load takes no
-//     vector address arithmetic at all.
+//   - A feature op's constant slot holds the byte offset of its row in an X
+//     tile.  Features are read through a buffer resource over the block's
+//     tile: the scalar offset is the row's offset and each lane's fixed
+//     32-bit byte offset (its pair of cases) is the vector offset, so a
+//     feature load takes no vector address arithmetic.
 //   - Both function forms share one `apply` (tos = f(tos, b)): a function of
 //     the top two values first moves them into place.
 //   - The program ends at its end word (kOpEnd), tested only on the push
 //     path, instead of a count compared before every op.
+//   - REG = 1 keeps a third stack value (n2, element d - 3) in registers as
+//     well, so that a program needs one LDS value per lane fewer (the LDS
+//     column is what bounds the resident waves of the deeper lists).
 // The FP64 operations and their order are those of eval_program, so results
 // are the same bits.
-template <int V, typename Stack>
+template <int V, int REG, typename Stack>
 __device__ __forceinline__ void eval_program_wide(const int32_t* ops, const double* opv, const double* opy,
                                                   const double* X, bool short_feature_div,
                                                   const uint32_t (&off)[V], Stack stk, int lane, double (&out)[V]) {
+  static_assert(REG == 0 || REG == 1, "two or three stack values in registers");
   constexpr int kBatch = kOpPad;
   const GSGP_CONST int32_t* cops = (const GSGP_CONST int32_t*)ops;
   const GSGP_CONST double* copv = (const GSGP_CONST double*)opv;
   const GSGP_CONST double* copy = (const GSGP_CONST double*)opy;
-  double tos[V], nos[V];
+  double tos[V], nos[V], n2[V];
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     tos[v] = 0.0;
     nos[v] = 0.0;
+    n2[v] = 0.0;
   }
   // raw buffer over X: no stride, num_records at the largest offset, and the
   // third descriptor word of a plain dword buffer on gfx9-family parts
@@ -479,16 +481,34 @@ __device__ __forceinline__ void eval_program_wide(const int32_t* ops, const doub
         else
           divide_by(b);
         const int d = (w >> 4) & kOpDepthMax;
-        if (d >= 3) {
+        if constexpr (REG == 0) {
+          if (d >= 3) {
 #pragma unroll
-          for (int v = 0; v < V; ++v) nos[v] = stk[((d - 3) * V + v) * kWave + lane];
+            for (int v = 0; v < V; ++v) nos[v] = stk[((d - 3) * V + v) * kWave + lane];
+          }
+        } else {
+#pragma unroll
+          for (int v = 0; v < V; ++v) nos[v] = n2[v];
+          if (d >= 4) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) n2[v] = stk[((d - 4) * V + v) * kWave + lane];
+          }
         }
-      } else {  // push: nos to LDS, tos to nos, the terminal to tos
+      } else {  // push: the lowest register value to LDS, the rest down one, the terminal to tos
         if (w & 2) goto done;  // kOpEnd
         const int d = (w >> 4) & kOpDepthMax;
-        if (d >= 2) {
+        if constexpr (REG == 0) {
+          if (d >= 2) {
 #pragma unroll
-          for (int v = 0; v < V; ++v) stk[((d - 2) * V + v) * kWave + lane] = nos[v];
+            for (int v = 0; v < V; ++v) stk[((d - 2) * V + v) * kWave + lane] = nos[v];
+          }
+        } else {
+          if (d >= 3) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) stk[((d - 3) * V + v) * kWave + lane] = n2[v];
+          }
+#pragma unroll
+          for (int v = 0; v < V; ++v) n2[v] = nos[v];
         }
 #pragma unroll
         for (int v = 0; v < V; ++v) nos[v] = tos[v];
@@ -602,7 +622,7 @@ __global__ __launch_bounds__(256) void k_interpret(const RunDev* __restrict__ ru
     const int need = uni(cload(&R.need[prog]));
     if (need <= lo || need > slots) continue;
     double out[kInterpV];
-    eval_program_wide<kInterpV>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k,
+    eval_program_wide<kInterpV, 0>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k,
                                 R.opy + (int64_t)prog * p.k, R.X + (first / kXTile) * R.l * kXTile,
                                 uni(R.x_big) == 0, off, (LdsStack)stk, lane, out);
     store_program<T, kInterpV>(R, p, prog, col, ok, out);
@@ -627,12 +647,12 @@ static_assert(kXTile == 4 * kWave && kXTile % kInterpTile == 0, "interpreter cas
 static_assert(65535LL * kXTile * sizeof(double) < (1LL << 31), "a tile of the most features the runtime accepts "
                                                                   "takes 32-bit buffer offsets");
 
-template <typename T, int SLOTS, int V>
+template <typename T, int SLOTS, int V, int REG>
 __global__ __launch_bounds__(kWave) void k_interpret_wide(const RunDev* __restrict__ runs, Params p, int32_t pgroups,
                                                           int lo, int list) {
   static_assert(V == 2 || V == 4, "two or four cases per lane");
   constexpr int kTile = kWave * V;
-  __shared__ double lds[SLOTS * V * kWave];
+  __shared__ double lds[(SLOTS - REG) * V * kWave];
   const int lane = threadIdx.x & 63;
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t cbg = blk / pgroups;  // case block over all runs
@@ -650,7 +670,7 @@ __global__ __launch_bounds__(kWave) void k_interpret_wide(const RunDev* __restri
   uint32_t off[V];
   lane_cases<V>(first, lane, R.ld, col, ok, off);
   double out[V];
-  eval_program_wide<V>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k, R.opy + (int64_t)prog * p.k,
+  eval_program_wide<V, REG>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k, R.opy + (int64_t)prog * p.k,
                        R.X + (first / kXTile) * R.l * kXTile, uni(R.x_big) == 0, off, (LdsStack)lds, lane, out);
   store_program<T, V>(R, p, prog, col, ok, out);
 }
@@ -684,7 +704,7 @@ __global__ __launch_bounds__(64) void k_interpret_spill(const RunDev* __restrict
       uint32_t off[kInterpV];
       lane_cases<kInterpV>(first, lane, R.ld, col, ok, off);
       double out[kInterpV];
-      eval_program_wide<kInterpV>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k,
+      eval_program_wide<kInterpV, 0>(R.ops + (int64_t)prog * p.k, R.opv + (int64_t)prog * p.k,
                                   R.opy + (int64_t)prog * p.k, R.X + (first / kXTile) * R.l * kXTile,
                                   uni(R.x_big) == 0, off, (GlobalStack)stk, lane, out);
       store_program<T, kInterpV>(R, p, prog, col, ok, out);
@@ -806,13 +826,18 @@ hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_
 // Section 3.1 shape with 2,047 genes; two cases per lane on the other lists
 // was slower).
 constexpr int kListV[kLists - 1] = {4, 4, 4, 2};
+// Stack values kept in registers beyond the top two (see eval_program_wide):
+// one more on the 4- and 6-value lists, whose LDS columns then shrink to 3
+// and 5 values (2,047 genes at the Section 3.1 shape: 222 -> 216 ms; on the
+// 3-value list as well it was slower, 223 ms).
+constexpr int kListReg[kLists - 1] = {0, 0, 1, 1};
 
 template <typename T, int B>
 void launch_wide_list(const RunDev* d_runs, const Params& p, int64_t case_blocks, int32_t progs, int lo, int list,
                       hipStream_t s) {
   const dim3 grid((unsigned)(case_blocks * progs));
-  hipLaunchKernelGGL((k_interpret_wide<T, kListSlots[B], kListV[B]>), grid, dim3(kWave), 0, s, d_runs, p, progs, lo,
-                     list);
+  hipLaunchKernelGGL((k_interpret_wide<T, kListSlots[B], kListV[B], kListReg[B]>), grid, dim3(kWave), 0, s, d_runs, p,
+                     progs, lo, list);
 }
 
 template <typename T>
