@@ -82,6 +82,9 @@ def vary_bytes(rec: np.ndarray, n_all: int, s: int, m: int) -> int:
 
 
 FP64_VALU_OPS = 78.6e12 / 2  # FP64 vector operations/s (the vendor FLOP/s counts an FMA as two)
+# L2 read bandwidth into the CUs: 8 XCDs x 16 L2 channels x 128 bytes per
+# clock at 2.4 GHz (the path that feeds the interpreter its feature rows)
+L2_READ_GBPS = 8 * 16 * 128 * 2.4
 PROBE = os.path.join(ROOT, "paper_2106_04034_amd", "copy_probe")
 
 
@@ -106,17 +109,27 @@ def gene_steps(codes: np.ndarray) -> int:
 
 def gene_steps_rows(codes: np.ndarray) -> np.ndarray:
     """gene_steps of each genome row."""
+    return gene_work_rows(codes)[0]
+
+
+def gene_work_rows(codes: np.ndarray):
+    """Per genome row: its gene-steps and the feature pushes among them (each
+    reads one feature value per case)."""
     depth = np.zeros(codes.shape[0], np.int64)
     ops = np.zeros(codes.shape[0], np.int64)
+    feats = np.zeros(codes.shape[0], np.int64)
     last = np.zeros(codes.shape[0], np.int64)
+    last_feats = np.zeros(codes.shape[0], np.int64)
     for q in range(codes.shape[1]):
         c = codes[:, q]
         push = (c >= 0) | (c == -5)
         fn = ~push & (depth >= 2)
         ops += push | fn
+        feats += c >= 0
         depth += push.astype(np.int64) - fn.astype(np.int64)
         last = np.where(fn, ops, last)
-    return last
+        last_feats = np.where(fn, feats, last_feats)
+    return last, last_feats
 
 
 def interpreter_rate(codes: np.ndarray, n_cases: int, ms: float) -> dict:
@@ -126,13 +139,19 @@ def interpreter_rate(codes: np.ndarray, n_cases: int, ms: float) -> dict:
 def interpreter_rate_rows(codes: np.ndarray, n_cases: np.ndarray, ms: float) -> dict:
     """Gene-steps/s of ComputeSemantics when genome row j runs on n_cases[j]
     cases (runs of uneven size in one handle)."""
-    steps = int(np.sum(gene_steps_rows(codes) * np.asarray(n_cases, np.int64)))
+    rows, feats = gene_work_rows(codes)
+    n = np.asarray(n_cases, np.int64)
+    steps = int(np.sum(rows * n))
+    feature_bytes = int(np.sum(feats * n)) * 8
     rate = steps / (ms * 1e-3)
-    return {"bound": "alu", "gene_steps": steps, "gene_steps_per_s": rate, "peak_fp64_ops_per_s": FP64_VALU_OPS,
-            "frac": rate / FP64_VALU_OPS, "compute_semantics_ms": ms,
-            "note": "one gene-step is one push or one valid function on one case; the peak is the FP64 vector "
-                    "operation rate, while a function step costs about three FP64 operations (the function and "
-                    "the clamp) plus the interpretive dispatch"}
+    feature_gbps = feature_bytes / (ms * 1e-3) / 1e9
+    return {"bound": "l2", "gene_steps": steps, "gene_steps_per_s": rate,
+            "feature_bytes": feature_bytes, "feature_GBps": feature_gbps, "peak_l2_read_GBps": L2_READ_GBPS,
+            "frac": feature_gbps / L2_READ_GBPS, "peak_fp64_ops_per_s": FP64_VALU_OPS,
+            "frac_fp64_ops": rate / FP64_VALU_OPS, "compute_semantics_ms": ms,
+            "note": "one gene-step is one push or one valid function on one case; feature_bytes are the FP64 "
+                    "feature values those steps read (8 bytes per feature push per case), which come from L2 "
+                    "through each CU's vector memory path, the unit the interpreter's counters show saturated"}
 
 
 def traffic_from_profile(path: str):

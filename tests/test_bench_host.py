@@ -80,6 +80,16 @@ def test_gene_steps_count_pushes_and_valid_functions_up_to_the_last_function(k):
     assert bench.gene_steps(hand) == 5
 
 
+def test_interpreter_feature_bytes_count_feature_pushes_up_to_the_last_function():
+    # "x0 x1 + c - x2": the trailing x2 never runs; x0 and x1 are read per case
+    hand = np.array([[0, 1, -1, -5, -2, 2], [3, -1, -1, -1, 0, 1], [-5, 4, -3, 0, -4, -4]], np.int32)
+    steps, feats = bench.gene_work_rows(hand)
+    assert list(steps) == [5, 0, 5] and list(feats) == [2, 0, 2]
+    rate = bench.interpreter_rate(hand, 10, 1.0)
+    assert rate["feature_bytes"] == 4 * 10 * 8
+    assert abs(rate["feature_GBps"] - 320 / 1e-3 / 1e9) < 1e-12
+
+
 def test_traffic_comes_from_the_counter_summary_only_for_the_same_kernel_sources(monkeypatch, tmp_path):
     path = tmp_path / "k_vary_x_pmc.md"
     path.write_text("# summary\n\nhbm_bytes_per_launch: 1234567890\nkernel_source_sha256_16: 0123456789abcdef\n")
