@@ -242,6 +242,39 @@ def test_deep_programs_take_the_second_interpreter_pass():
     R.close()
 
 
+@pytest.mark.parametrize("precision", [gsgp.FP64, gsgp.FP32])
+def test_every_stack_need_list_matches_the_oracle(precision):
+    """Each interpreter pass over a stack-need list (needs up to 2, 3, 4,
+    5-6, 7-63 and the spill pass beyond) takes programs of its own, among
+    Philox genomes of 2,047 genes (most of which need 3 to 6 LDS values),
+    and programs built to need exactly 1 to 9 and 70 values; a ragged case
+    count spans several 256-case tiles.  FP64 semantics are the oracle's bits;
+    FP32 storage holds the oracle's value rounded once."""
+    rng = np.random.default_rng(2047)
+    k, l, m, r = 2047, 6, 96, 32
+    s = gsgp.Settings(pop_size=m, pool_size=r, genome_len=k, n_generations_max=1, seed=77, precision=precision)
+    d = dataset(700, 131, l, seed=60)
+    ocfg = oracle_config(s)
+    cp, vp = orc.genomes(ocfg, l, orc.TAG_POPULATION, m)
+    cr, vr = orc.genomes(ocfg, l, orc.TAG_POOL, r)
+    codes, consts = np.concatenate([cp, cr]), np.concatenate([vp, vr])
+    for row, D in enumerate((3, 4, 5, 6, 7, 8, 9, 10, 11, 72)):
+        codes[row * 3], consts[row * 3] = _deep_genome(rng, D, k, l)
+    need = _stack_depths(codes) - 2
+    for lo, hi in ((-9, 2), (3, 3), (4, 4), (5, 6), (7, 63), (64, 10 ** 6)):
+        assert ((need >= lo) & (need <= hi)).sum() >= 1, (lo, hi)
+    R = _runner(s, [d])
+    R.eval_population(codes, consts)
+    X = np.concatenate([d.X_train, d.X_test])
+    want = orc.interpret(codes[:m], consts[:m], X)
+    got = R.semantics(0, 0)
+    if precision == gsgp.FP64:
+        assert np.array_equal(got, want)
+    else:
+        assert np.array_equal(got, want.astype(np.float32).astype(np.float64))
+    R.close()
+
+
 def test_terminals_after_the_last_function_do_not_count_towards_the_stack_limit():
     """Only the stack up to a genome's last valid function limits what the
     interpreter accepts: 100 terminals after it (or a genome of terminals
