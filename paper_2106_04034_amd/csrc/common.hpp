@@ -206,9 +206,10 @@ hipError_t launch_compile(const RunDev* d_runs, const Params& p, hipStream_t s);
 // Interpreter passes: each takes the programs of stack-need list `list` (at
 // most `progs` per run) with lo < need <= slots.  launch_interpret: two
 // cases per lane, any slots up to kMaxLdsSlots, case_blocks blocks of
-// kInterpCases cases; launch_interpret_wide: list < kLists - 1 with its
-// LDS column of kListSlots[list] values, two or four cases per lane (blocks
-// of kInterpCases or kXTile cases over all runs: blocks128, blocks256).
+// kInterpCases cases; launch_interpret_wide: list < kLists - 1, whose
+// programs need at most kListSlots[list] values, two or four cases per lane
+// (blocks of kInterpCases or kXTile cases over all runs: blocks128,
+// blocks256).
 hipError_t launch_interpret(const RunDev* d_runs, const Params& p, int64_t case_blocks, int lo, int slots,
                             int list, int32_t progs, hipStream_t s);
 hipError_t launch_interpret_wide(const RunDev* d_runs, const Params& p, int64_t blocks256, int64_t blocks128, int lo,
