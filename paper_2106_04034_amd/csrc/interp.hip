@@ -61,76 +61,108 @@ __device__ __forceinline__ double div_short(double a, double b, double y) {
 // Compile a genome: drop the functions the stack machine would skip (fewer
 // than two operands) and everything after the last function that runs, and
 // store each op's stack depth so the interpreter needs no depth counter.
-// One thread per genome; also records the deepest stack per run.
-__global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs, Params p,
-                                                 int32_t total) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= total) return;
+// One thread per genome, one wave per block of 64 genomes of one run; also
+// records the deepest stack per run.  The wave stages its genomes' codes
+// and constants in LDS kCompileChunk genes at a time with coalesced loads
+// (a genome row per load instruction), so each thread walks its genome
+// from LDS instead of with one scattered load per gene.
+constexpr int kCompileChunk = 64;
+
+__global__ __launch_bounds__(kWave) void k_compile(const RunDev* __restrict__ runs, Params p, int32_t groups) {
+  __shared__ int32_t s_code[kWave][kCompileChunk + 1];
+  __shared__ double s_cval[kWave][kCompileChunk + 1];
+  const int lane = threadIdx.x;
   const int rows = p.m + p.r;
-  const int run = g / rows;
-  const int prog = g - run * rows;
+  const int run = blockIdx.x / groups;
+  const int prog0 = (blockIdx.x - run * groups) * kWave;
+  const int prog = prog0 + lane;
+  const bool mine = prog < rows;
   const RunDev& R = runs[run];
-  const int32_t* code = R.code + (int64_t)prog * p.k;
-  const double* cval = R.cval + (int64_t)prog * p.k;
   int32_t* ops = R.ops + (int64_t)prog * p.k;
   double* opv = R.opv + (int64_t)prog * p.k;
   double* opy = R.opy + (int64_t)prog * p.k;
   // deepest: the deepest stack up to the last valid function; pushes after
   // it are dropped and never run, so they do not count
   int depth = 0, n = 0, last = 0, deepest = 0, peak = 0;
-  int32_t prev = 0;  // the last op word written, ops[n - 1]
-  for (int q = 0; q < p.k; ++q) {
-    const int32_t c = code[q];
-    // depths before the last function are at most k - 1 <= kOpDepthMax, and
-    // ops after the last function never run; the cap only keeps the field
-    // inside its bits
-    const int dfield = (depth < kOpDepthMax ? depth : kOpDepthMax) << 4;
-    if (c >= 0) {
-      prev = (kClsPush << 2) | kPushFeature | dfield | (c << 16);
-      ops[n] = prev;
-      // the byte offset of the feature's row in a tile of this run's X, bit
-      // for bit (see eval_program)
-      opv[n] = __longlong_as_double((long long)((int64_t)c * kXTile * (int64_t)sizeof(double)));
-      opy[n] = 0.0;
-      ++n;
-      ++depth;
-    } else if (c == -5) {
-      prev = (kClsPush << 2) | kPushConst | dfield;
-      ops[n] = prev;
-      opv[n] = cval[q];
-      opy[n] = 0.0;
-      ++n;
-      ++depth;
-    } else {
-      if (depth < 2) continue;  // skipped by the interpreter
-      const int fn = -1 - c;
-      if (n > 0 && ((prev >> 2) & 3) == kClsPush) {
-        // push b, then op(a, b) with a the value below it: one op on the top
-        // of the stack; the depth field stays the one before the push, the
-        // feature index and the constant stay where the push put them
-        const int cls = (prev & 3) == kPushConst ? kClsConst : kClsFeature;
-        prev = (prev & ~0xF) | (cls << 2) | fn;
-        ops[n - 1] = prev;
-        if (cls == kClsConst && fn == kFnDiv) {
-          // a constant divisor in the short division's range: its reciprocal
-          // refinement, once (0 selects the full division)
-          const double b = opv[n - 1];
-          const double ab = fabs(b);
-          opy[n - 1] = ab >= kDivShortMinDivisor && ab <= kDivShortMaxDivisor ? div_recip(b) : 0.0;
-        }
-      } else {
-        prev = (kClsStack << 2) | fn | dfield;
+  int32_t prev = 0;   // the last op word written, ops[n - 1]
+  double prevv = 0;   // and its constant slot, opv[n - 1]
+  for (int q0 = 0; q0 < p.k; q0 += kCompileChunk) {
+    const int len = p.k - q0 < kCompileChunk ? p.k - q0 : kCompileChunk;
+    __syncthreads();  // the previous chunk is consumed
+    for (int i = 0; i < kWave && prog0 + i < rows; ++i) {
+      if (lane < len) {
+        const int64_t at = (int64_t)(prog0 + i) * p.k + q0 + lane;
+        s_code[i][lane] = R.code[at];
+        s_cval[i][lane] = R.cval[at];
+      }
+    }
+    __syncthreads();
+    if (!mine) continue;
+    for (int u = 0; u < len; ++u) {
+      const int32_t c = s_code[lane][u];
+      // depths before the last function are at most k - 1 <= kOpDepthMax, and
+      // ops after the last function never run; the cap only keeps the field
+      // inside its bits
+      const int dfield = (depth < kOpDepthMax ? depth : kOpDepthMax) << 4;
+      if (c >= 0) {
+        prev = (kClsPush << 2) | kPushFeature | dfield | (c << 16);
+        // the byte offset of the feature's row in a tile of this run's X,
+        // bit for bit (see eval_program)
+        prevv = __longlong_as_double((long long)((int64_t)c * kXTile * (int64_t)sizeof(double)));
         ops[n] = prev;
-        opv[n] = 0.0;
+        opv[n] = prevv;
         opy[n] = 0.0;
         ++n;
+        ++depth;
+      } else if (c == -5) {
+        prev = (kClsPush << 2) | kPushConst | dfield;
+        prevv = s_cval[lane][u];
+        ops[n] = prev;
+        opv[n] = prevv;
+        opy[n] = 0.0;
+        ++n;
+        ++depth;
+      } else {
+        if (depth < 2) continue;  // skipped by the interpreter
+        const int fn = -1 - c;
+        if (n > 0 && ((prev >> 2) & 3) == kClsPush) {
+          // push b, then op(a, b) with a the value below it: one op on the
+          // top of the stack; the depth field stays the one before the push,
+          // the feature index and the constant stay where the push put them
+          const int cls = (prev & 3) == kPushConst ? kClsConst : kClsFeature;
+          prev = (prev & ~0xF) | (cls << 2) | fn;
+          ops[n - 1] = prev;
+          if (cls == kClsConst && fn == kFnDiv) {
+            // a constant divisor in the short division's range: its
+            // reciprocal refinement, once (0 selects the full division)
+            const double ab = fabs(prevv);
+            opy[n - 1] = ab >= kDivShortMinDivisor && ab <= kDivShortMaxDivisor ? div_recip(prevv) : 0.0;
+          }
+        } else {
+          prev = (kClsStack << 2) | fn | dfield;
+          prevv = 0.0;
+          ops[n] = prev;
+          opv[n] = 0.0;
+          opy[n] = 0.0;
+          ++n;
+        }
+        --depth;
+        last = n;
+        deepest = peak;
       }
-      --depth;
-      last = n;
-      deepest = peak;
+      peak = depth > peak ? depth : peak;
     }
-    peak = depth > peak ? depth : peak;
   }
+  // the run's deepest stack: one atomic per wave (one per genome put every
+  // genome of a run on one address, serialised at one L2 channel)
+  int dmax = mine ? deepest : 0;
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const int other = __shfl_xor(dmax, o);
+    dmax = other > dmax ? other : dmax;
+  }
+  if (lane == 0) atomicMax(&R.state[kStMaxDepth], dmax);
+  if (!mine) return;
   R.nops[prog] = last;
   // the end word of eval_program_wide: a program with a valid function
   // starts with a push fused into it, so last <= k - 1 and the word stays in
@@ -138,7 +170,6 @@ __global__ __launch_bounds__(256) void k_compile(const RunDev* __restrict__ runs
   ops[last] = kOpEnd;
   const int need = deepest > 2 ? deepest - 2 : 0;  // the top two values live in registers
   R.need[prog] = need;
-  atomicMax(&R.state[kStMaxDepth], deepest);
 }
 
 // Files each run's programs into the stack-need lists, each list in order
@@ -789,8 +820,8 @@ inline int interp_waves(int slots) {
 }  // namespace
 
 hipError_t launch_compile(const RunDev* d_runs, const Params& p, hipStream_t s) {
-  const int32_t total = p.n_runs * (p.m + p.r);
-  hipLaunchKernelGGL(k_compile, dim3(blocks_for(total, 256)), dim3(256), 0, s, d_runs, p, total);
+  const int32_t groups = (p.m + p.r + kWave - 1) / kWave;  // 64-genome groups per run
+  hipLaunchKernelGGL(k_compile, dim3((unsigned)p.n_runs * groups), dim3(kWave), 0, s, d_runs, p, groups);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // length bins: (k - length) >> shift < kOrderBins for lengths 0 .. k
